@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs shared by the GPU path, the tests and the benchmark.
+
+This module holds no part of the SMC method: it only builds the data a run is
+conditioned on (observed trees, observation series, request streams) and the
+plain model specifications (dicts of parameters) that both the GPU binding and
+the CPU checker accept. Random numbers here come from NumPy's PCG64 generator
+and never from the method's own Philox streams.
+
+Model specifications (``params`` positions are part of the C interface):
+
+* ``geometric`` (Sec. 2, Fig. 2): params = [p_heads, weight factor];
+  ``checkpoint`` = resample after every heads (else one importance-sampling pass).
+* ``lgssm`` (eq. (2), Fig. 4): params = [a, b, q_sd, r_sd, m0, s0_sd];
+  x_0 ~ N(m0, s0), x_t = a x_{t-1} + b + N(0, q), y_t ~ N(x_t, r).
+* ``crbd`` (Appendix B listing): params = [rho, lambda scale, mu scale,
+  fixed lambda (>0 fixes it), fixed mu (>=0 fixes it), max hidden events,
+  max recursion depth]; priors lambda ~ Gamma(1, scale), mu ~ Gamma(1, scale).
+* ``clads``: params = [rho, lambda0 scale, eps lo, eps hi, alpha lo, alpha hi,
+  sigma scale, max events, max depth, fixed lambda0 (>0), fixed eps (>=0),
+  fixed alpha (>0), fixed sigma (>=0)].
+
+Trees are binary, ultrametric, in preorder with the root at index 0 and the
+left subtree before the right one; ``age`` is time before the present.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MAX_EVENTS = 10_000
+MAX_DEPTH = 32
+
+
+def yule_tree(n_tips: int, seed: int) -> dict:
+    """Rate-1 Yule tree with ``n_tips`` tips, scaled to root age 1.0.
+
+    Forward in time from a root split into two lineages: while there are k < n
+    lineages, wait Exp(rate k) and split a uniformly chosen lineage (its left
+    daughter keeps the lineage's slot); then wait a final Exp(rate n) to the
+    present. Ages are measured back from the present and divided by the root
+    age. Returned arrays are in preorder (root 0, left subtree first).
+    """
+    if n_tips < 2:
+        raise ValueError("a tree needs at least two tips")
+    rng = np.random.default_rng(seed)
+    time = [0.0]                 # birth time of each node's lineage split (internal) / present (tips)
+    children: list[tuple[int, int] | None] = [None]
+    active = []
+    for _ in range(2):
+        time.append(0.0)
+        children.append(None)
+        active.append(len(time) - 1)
+    children[0] = (active[0], active[1])
+    t = 0.0
+    while len(active) < n_tips:
+        k = len(active)
+        t += rng.exponential(1.0 / k)
+        idx = int(rng.integers(k))
+        node = active[idx]
+        time[node] = t
+        a = len(time); time.append(0.0); children.append(None)
+        b = len(time); time.append(0.0); children.append(None)
+        children[node] = (a, b)
+        active[idx] = a
+        active.append(b)
+    t += rng.exponential(1.0 / n_tips)
+    for node in active:
+        time[node] = t
+    root_age = t - time[0]
+    # preorder relabelling
+    order = []
+    stack = [0]
+    while stack:
+        v = stack.pop()
+        order.append(v)
+        ch = children[v]
+        if ch is not None:
+            stack.append(ch[1])
+            stack.append(ch[0])
+    new_id = {v: i for i, v in enumerate(order)}
+    n_nodes = len(order)
+    parent = np.full(n_nodes, -1, dtype=np.int32)
+    left = np.full(n_nodes, -1, dtype=np.int32)
+    right = np.full(n_nodes, -1, dtype=np.int32)
+    age = np.zeros(n_nodes, dtype=np.float64)
+    for v in order:
+        i = new_id[v]
+        age[i] = (t - time[v]) / root_age
+        ch = children[v]
+        if ch is not None:
+            left[i] = new_id[ch[0]]
+            right[i] = new_id[ch[1]]
+            parent[new_id[ch[0]]] = i
+            parent[new_id[ch[1]]] = i
+    age[left < 0] = 0.0
+    age[0] = 1.0
+    return {"parent": parent, "left": left, "right": right, "age": age, "tips": n_tips}
+
+
+def tree_from_newick_like(spec) -> dict:
+    """Tree from nested tuples ``(left, right, age)`` with tips given as ``0.0``
+    (their age). Used for tiny hand-made test trees."""
+    nodes = []
+
+    def visit(node, par):
+        i = len(nodes)
+        if isinstance(node, tuple):
+            nodes.append([par, -1, -1, float(node[2])])
+            nodes[i][1] = visit(node[0], i)
+            nodes[i][2] = visit(node[1], i)
+        else:
+            nodes.append([par, -1, -1, float(node)])
+        return i
+
+    visit(spec, -1)
+    parent = np.array([n[0] for n in nodes], dtype=np.int32)
+    left = np.array([n[1] for n in nodes], dtype=np.int32)
+    right = np.array([n[2] for n in nodes], dtype=np.int32)
+    age = np.array([n[3] for n in nodes], dtype=np.float64)
+    return {"parent": parent, "left": left, "right": right, "age": age,
+            "tips": int((left < 0).sum())}
+
+
+def lgssm_data(T: int, seed: int, a=0.9, b=0.0, q=1.0, r=0.5, m0=0.0, s0=None) -> np.ndarray:
+    """Simulate y_1..y_T from the linear-Gaussian model (x_0 ~ N(m0, s0))."""
+    if s0 is None:
+        s0 = math.sqrt(q * q / (1.0 - a * a))
+    rng = np.random.default_rng(seed)
+    x = m0 + s0 * rng.standard_normal()
+    y = np.empty(T, dtype=np.float64)
+    for t in range(T):
+        x = a * x + b + q * rng.standard_normal()
+        y[t] = x + r * rng.standard_normal()
+    return y
+
+
+def geometric_spec(checkpoint=True, p=0.5, w=1.5) -> dict:
+    return {"kind": "geometric", "precision": 64, "checkpoint": bool(checkpoint),
+            "params": [p, w]}
+
+
+def lgssm_spec(y, precision=32, a=0.9, b=0.0, q=1.0, r=0.5, m0=0.0, s0=None) -> dict:
+    if s0 is None:
+        s0 = math.sqrt(q * q / (1.0 - a * a))
+    return {"kind": "lgssm", "precision": precision, "y": np.asarray(y, dtype=np.float64),
+            "params": [a, b, q, r, m0, s0]}
+
+
+def crbd_spec(tree, precision=64, rho=1.0, scale_lambda=1.0, scale_mu=0.5,
+              fixed_lambda=0.0, fixed_mu=-1.0, max_events=MAX_EVENTS, max_depth=MAX_DEPTH) -> dict:
+    return {"kind": "crbd", "precision": precision, "tree": tree,
+            "params": [rho, scale_lambda, scale_mu, fixed_lambda, fixed_mu,
+                       float(max_events), float(max_depth)]}
+
+
+def clads_spec(tree, precision=32, rho=1.0, scale_l0=1.0, eps=(0.0, 1.0), alpha=(0.8, 1.1),
+               scale_sigma=0.2, max_events=MAX_EVENTS, max_depth=MAX_DEPTH,
+               fixed_l0=0.0, fixed_eps=-1.0, fixed_alpha=0.0, fixed_sigma=-1.0) -> dict:
+    return {"kind": "clads", "precision": precision, "tree": tree,
+            "params": [rho, scale_l0, eps[0], eps[1], alpha[0], alpha[1], scale_sigma,
+                       float(max_events), float(max_depth), fixed_l0, fixed_eps,
+                       fixed_alpha, fixed_sigma]}
+
+
+def request_stream(n_requests: int, seed: int, rate_per_s: float,
+                   tips=(16, 512), log2_particles=(10, 18)) -> list[dict]:
+    """Serving workload: Poisson arrivals; each request is CRBD or ClaDS (1/2 each)
+    on a fresh Yule tree with round(2^U(log2 lo, log2 hi)) tips and
+    N = 2^k particles, k uniform on the integer range."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    lo, hi = math.log2(tips[0]), math.log2(tips[1])
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate_per_s)
+        kind = "crbd" if rng.random() < 0.5 else "clads"
+        n_tips = int(round(2.0 ** rng.uniform(lo, hi)))
+        n_tips = min(max(n_tips, tips[0]), tips[1])
+        k = int(rng.integers(log2_particles[0], log2_particles[1] + 1))
+        tree_seed = int(rng.integers(1 << 31))
+        run_seed = int(rng.integers(1 << 62))
+        out.append({"id": i, "arrival": t, "kind": kind, "tips": n_tips, "n": 1 << k,
+                    "tree_seed": tree_seed, "seed": run_seed})
+    return out

