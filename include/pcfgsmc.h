@@ -1,0 +1,219 @@
+/*
+ * pcfgsmc -- SMC over PPL control-flow graphs on AMD Instinct MI355X (gfx950).
+ *
+ * C interface of libpcfgsmc.so. It follows the statement of the problem in
+ * Lunden et al., "Compiling Universal Probabilistic Programming Languages with
+ * Efficient Parallel Sequential Monte Carlo Inference" (ESOP 2022):
+ *
+ *   smc_model_register  <->  a PCFG (B, S, sim, b0, b_stop, L)          Sec. 3.1
+ *   smc_init            <->  Algorithm 1, step 1 (initialisation)      Sec. 3.2
+ *   smc_step            <->  Algorithm 1, step 2 (propagation)         Sec. 3.2
+ *   smc_resample        <->  Algorithm 1, step 3 (resampling), with the
+ *                            systematic scheme and the normalising-constant
+ *                            estimate of the RootPPL engine              Sec. 3.3
+ *   smc_done            <->  the engine's termination check            Sec. 3.3
+ *   smc_log_z           <->  the normalising-constant estimate          Sec. 3.3
+ *
+ * Conventions
+ *  - Every handle is opaque. Every function returns an smc_status; no C++
+ *    exception crosses this interface. On an error, smc_last_error() returns a
+ *    thread-local message describing the most recent failure on that thread.
+ *  - Pointers marked "host" are ordinary CPU memory owned by the caller and
+ *    only read (or written, for outputs) during the call. Device memory is
+ *    allocated by the library through the context's allocator and released by
+ *    the matching destroy call.
+ *  - Work is enqueued on the context's HIP stream and runs asynchronously.
+ *    smc_done, smc_log_z, smc_read, smc_run_stats, smc_batch_poll,
+ *    smc_resample_weights, the self-tests and the destroy calls synchronise
+ *    with that stream.
+ *  - Runs are deterministic: the same model, particle count and seed give the
+ *    same ancestors, block indices and states, alone or inside a batch.
+ *
+ * Random numbers. Word k drawn by particle n in round r is word (k mod 4) of
+ * Philox4x32-10 (Salmon et al., SC'11) with counter {k/4, n, r, 0} and key
+ * {seed & 0xffffffff, seed >> 32}; the resampling offset of round r is word 0
+ * of counter {0, 0, r, 1}. A uniform from word w is (2w + 1) 2^-33.
+ *
+ * Resampling. With M = max lw, w_n = exp(lw_n - M) is rounded to the grid
+ * 2^-G, G = min(32, 53 - ceil(log2 N)), so the FP64 prefix sums are exact; with
+ * Q_n the inclusive sums and U the round's offset word, output j takes the
+ * ancestor a_j = min{ i : N Q_i 2^32 > (j 2^32 + U) Q_{N-1} }. log Z gains
+ * (M + log sum_n exp(lw_n - M)) - log N per round, and once more, without
+ * resampling, when every particle has stopped.
+ */
+#ifndef PCFGSMC_H
+#define PCFGSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t smc_status;
+enum {
+    SMC_OK = 0,
+    SMC_FINISHED = 1,        /* informational: every particle reached b_stop */
+    SMC_ERR_INVALID = -1,    /* bad argument; nothing was allocated or enqueued */
+    SMC_ERR_OOM = -2,        /* the allocator returned NULL */
+    SMC_ERR_DEVICE = -3,     /* a HIP call failed; see smc_last_error() */
+    SMC_ERR_STATE = -4,      /* call out of order (e.g. two smc_step without smc_resample) */
+    SMC_ERR_NAN = -5,        /* a log-weight was NaN or +inf (a model bug) */
+    SMC_DEGENERATE = -6      /* every log-weight was -inf; log Z = -inf and the run stops */
+};
+
+typedef struct smc_ctx smc_ctx;
+typedef struct smc_model smc_model;
+typedef struct smc_run smc_run;
+typedef struct smc_batch smc_batch;
+
+/* Device-memory allocator. alloc(ctx, bytes) returns device memory or NULL;
+ * free(ctx, p) releases it. Both are called on the host thread that makes the
+ * library call. Passing NULL for the allocator selects hipMalloc / hipFree. */
+typedef struct {
+    void* (*alloc)(void* ctx, size_t bytes);
+    void (*free)(void* ctx, void* p);
+    void* ctx;
+} smc_allocator;
+
+/* Built-in block tables. */
+enum {
+    SMC_MODEL_GEOMETRIC = 0, /* Sec. 2, Fig. 2: weighted geometric program */
+    SMC_MODEL_LGSSM = 1,     /* eq. (2), Fig. 4: linear-Gaussian state-space model */
+    SMC_MODEL_CRBD = 2,      /* Appendix B listing: constant-rate birth-death */
+    SMC_MODEL_CLADS = 3      /* birth-death with cladogenetic rate shifts */
+};
+
+/* Model description (all pointers are host memory, deep-copied to the device
+ * by smc_model_register; the caller keeps ownership).
+ *
+ * precision: 32 or 64, the storage precision of real-valued particle state.
+ *   Block arithmetic is FP64; log-weights and resampling are always FP64.
+ * params, by kind (positions are part of the interface):
+ *   GEOMETRIC  {p_heads, weight factor}; checkpoint = 1 resamples after every
+ *              heads, 0 gives one importance-sampling pass.
+ *   LGSSM      {a, b, q_sd, r_sd, m0, s0_sd}: x0 ~ N(m0, s0),
+ *              x_t = a x_{t-1} + b + N(0, q), y_t ~ N(x_t, r); y has T entries.
+ *   CRBD       {rho, lambda scale, mu scale, fixed lambda (>0 fixes it),
+ *              fixed mu (>=0 fixes it), max hidden events, max depth}.
+ *   CLADS      {rho, lambda0 scale, eps lo, eps hi, alpha lo, alpha hi,
+ *              sigma scale, max events, max depth, fixed lambda0 (>0),
+ *              fixed eps (>=0), fixed alpha (>0), fixed sigma (>=0)}.
+ * Hidden-event budgets must lie in [0, 10^6] and recursion depths in [1, 32].
+ * Trees (CRBD, CLADS): n_nodes = 2 tips - 1 nodes in preorder, root 0, left
+ * subtree first; parent[root] = -1, left/right = -1 at tips; age = time before
+ * the present (tips 0). */
+typedef struct {
+    int32_t kind;
+    int32_t precision;
+    int32_t checkpoint;
+    int32_t n_nodes;
+    const int32_t* parent;
+    const int32_t* left;
+    const int32_t* right;
+    const double* age;
+    int32_t T;
+    const double* y;
+    double params[16];
+} smc_model_desc;
+
+/* Context: one device, one stream. stream is a hipStream_t (NULL = the null
+ * stream); allocator may be NULL. */
+smc_status smc_ctx_create(int32_t device, void* stream, const smc_allocator* allocator, smc_ctx** out);
+smc_status smc_ctx_destroy(smc_ctx* ctx); /* NULL-safe; the caller destroys runs, batches and models first */
+
+/* Register a PCFG (Sec. 3.1): validates the description and uploads constant
+ * data (tree arrays, observations). */
+smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* desc, smc_model** out);
+smc_status smc_model_destroy(smc_model* model); /* NULL-safe */
+
+/* Algorithm 1 step 1: N particles at block b0 with zero state and zero
+ * log-weight. N must be in [1, 2^24]. */
+smc_status smc_init(smc_model* model, uint64_t n_particles, uint64_t seed, smc_run** out);
+
+/* Algorithm 1 step 2: every particle not at b_stop runs blocks until a
+ * checkpoint or b_stop (one kernel launch). Must alternate with smc_resample. */
+smc_status smc_step(smc_run* run);
+
+/* Algorithm 1 step 3: log Z update, systematic ancestors, and the gather of
+ * (state, block) by ancestor (performed on read by the next smc_step). When
+ * every particle is at b_stop, only the log Z update runs and the run
+ * finishes. */
+smc_status smc_resample(smc_run* run);
+
+/* Termination check (synchronises): *done = 1 when the run finished,
+ * degenerated or failed; returns that status. */
+smc_status smc_done(smc_run* run, int32_t* done);
+
+/* Normalising-constant estimate so far (synchronises). */
+smc_status smc_log_z(smc_run* run, double* out);
+
+/* Step and resample until the run ends (checks termination every few rounds). */
+smc_status smc_run_to_end(smc_run* run);
+
+/* Copy per-particle data to a caller-owned host buffer (synchronises).
+ * what: SMC_READ_BLK (uint8 per particle; 255 = b_stop), SMC_READ_LW (double),
+ * SMC_READ_ANC (uint32: ancestors of the last resampling), or
+ * SMC_READ_FIELD0 + k for state field k in the model's field order (real fields
+ * in the storage precision, then int32 fields, then the ClaDS rate stack as
+ * [particle][level] with smc_run_stats().stack_depth levels). State is returned
+ * as Algorithm 1 holds it: after smc_resample, already gathered by ancestor.
+ * bytes must be at least the size of the array. */
+enum { SMC_READ_BLK = 0, SMC_READ_LW = 1, SMC_READ_ANC = 2, SMC_READ_FIELD0 = 16 };
+smc_status smc_read(smc_run* run, int32_t what, void* host_dst, size_t bytes);
+
+typedef struct {
+    uint32_t round;          /* rounds propagated so far */
+    int32_t status;          /* SMC_OK while running */
+    uint64_t block_steps;    /* executions of the model's blocks (b_stop excluded) */
+    double log_z;
+    int32_t stack_depth;     /* ClaDS: pending-rate stack levels per particle */
+} smc_stats;
+smc_status smc_run_stats(smc_run* run, smc_stats* out);
+
+smc_status smc_run_destroy(smc_run* run); /* NULL-safe */
+
+/* Resampling alone (Algorithm 1 step 3) on a device array of n log-weights:
+ * writes the log Z increment (device double) and the n ancestors (device
+ * uint32) for round `round` under `seed`. lw, anc and logz_inc are device
+ * pointers owned by the caller. Returns SMC_DEGENERATE / SMC_ERR_NAN as a run
+ * would (synchronises to report them). */
+smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint64_t seed,
+                                uint32_t round, uint32_t* anc, double* logz_inc);
+
+/* Batches: many independent runs advanced together (one launch per kernel
+ * for all runs; small runs run whole rounds inside one work-group).
+ * Results are identical to the same runs executed alone. */
+smc_status smc_batch_create(smc_ctx* ctx, smc_batch** out);
+/* Add a run (Algorithm 1 step 1 for it); *slot receives its index. */
+smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n_particles, uint64_t seed, int32_t* slot);
+/* Advance every live run by up to `rounds` rounds (step + resample each). */
+smc_status smc_batch_tick(smc_batch* b, int32_t rounds);
+/* Synchronises. done[i] = 1 for finished (or failed) slots; log_z[i] their
+ * estimates; status[i] their status. Arrays are host, length = slots. */
+smc_status smc_batch_poll(smc_batch* b, int32_t slots, int32_t* done, double* log_z, int32_t* status,
+                          uint64_t* block_steps);
+/* Free a finished slot's device memory; the slot may be reused by smc_batch_add. */
+smc_status smc_batch_retire(smc_batch* b, int32_t slot);
+smc_status smc_batch_destroy(smc_batch* b); /* NULL-safe */
+
+/* Self-test entry points: evaluate the device's pinned primitives on n inputs.
+ * in and out are device arrays of doubles.
+ * op 0 exp(x), 1 log(x), 2 cos(2 pi u), 3 sqrt(x), 4 uniform from word w
+ * (input = w as a double), 5 Box-Muller normal from the word pair
+ * (in[2i], in[2i+1]) -> out[i], 6 Poisson(in[2i]) drawn from the stream of
+ * seed in[2i+1] (an integer below 2^53), particle i, round 0, tag 0, from word
+ * 0 -> out[i] (-1 when the mean exceeds the event cap). */
+smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n);
+/* Philox4x32-10 on n counters: ctr (device, 4 x uint32 each), key (2 x uint32
+ * each), out (device, 4 x uint32 each). */
+smc_status smc_selftest_philox(smc_ctx* ctx, const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n);
+
+const char* smc_last_error(void);
+const char* smc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

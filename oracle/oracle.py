@@ -76,6 +76,9 @@ def lib():
     L.or_round.argtypes = [C.c_void_p]; L.or_round.restype = C.c_uint32
     L.or_block_steps.argtypes = [C.c_void_p]; L.or_block_steps.restype = C.c_uint64
     L.or_read.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]; L.or_read.restype = C.c_int32
+    L.or_propagate_particle.argtypes = [C.POINTER(_Model), C.c_uint64, C.c_uint32, C.c_uint32,
+                                        C.POINTER(C.c_uint8), f64p, f64p, C.POINTER(C.c_int32), f64p]
+    L.or_propagate_particle.restype = C.c_int32
     _lib = L
     return L
 
@@ -140,6 +143,59 @@ def systematic(lw, seed, rnd):
 
 
 # --- runs -----------------------------------------------------------------
+
+def _model_struct(spec, keep):
+    m = _Model()
+    m.kind = KINDS[spec["kind"]]
+    m.precision = int(spec.get("precision", 64))
+    m.checkpoint = int(bool(spec.get("checkpoint", True)))
+    tree = spec.get("tree")
+    if tree is not None:
+        arrs = {k: np.ascontiguousarray(tree[k], dtype=np.int32) for k in ("parent", "left", "right")}
+        age = np.ascontiguousarray(tree["age"], dtype=np.float64)
+        keep += list(arrs.values()) + [age]
+        m.n_nodes = len(age)
+        m.parent = _ptr(arrs["parent"], C.c_int32)
+        m.left = _ptr(arrs["left"], C.c_int32)
+        m.right = _ptr(arrs["right"], C.c_int32)
+        m.age = _ptr(age, C.c_double)
+    y = spec.get("y")
+    if y is not None:
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        keep.append(y)
+        m.T = len(y)
+        m.y = _ptr(y, C.c_double)
+    for i, v in enumerate(spec.get("params", [])):
+        m.p[i] = float(v)
+    return m
+
+
+N_REAL = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4}
+N_INT = {"geometric": 1, "lgssm": 1, "crbd": 1, "clads": 2}
+
+
+def propagate_particle(spec, seed, slot, rnd, blk, reals, ints, stack=None, stack_depth=0):
+    """Run one particle's blocks for round `rnd` in slot `slot` from the given state.
+    Returns (blk, lw, reals, ints, stack)."""
+    keep = []
+    m = _model_struct(spec, keep)
+    b = C.c_uint8(int(blk))
+    lw = C.c_double(0.0)
+    r = np.zeros(max(1, N_REAL[spec["kind"]]), dtype=np.float64)
+    r[:len(reals)] = reals
+    i = np.zeros(max(1, N_INT[spec["kind"]]), dtype=np.int32)
+    i[:len(ints)] = ints
+    st = None
+    if stack is not None:
+        st = np.zeros(stack_depth, dtype=np.float64)
+        st[:len(stack)] = stack
+    code = lib().or_propagate_particle(C.byref(m), int(seed), int(slot), int(rnd), C.byref(b), C.byref(lw),
+                                       _ptr(r, C.c_double), _ptr(i, C.c_int32),
+                                       _ptr(st, C.c_double) if st is not None else None)
+    if code != OK:
+        raise ValueError("oracle rejected the particle")
+    return int(b.value), lw.value, r, i, st
+
 
 class Run:
     """One SMC run of Algorithm 1 on the CPU oracle."""

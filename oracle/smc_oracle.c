@@ -640,21 +640,50 @@ void or_destroy(or_run* r)
 /* Alg. 1 step 2: every particle not at b_stop runs blocks until a           */
 /* checkpoint or b_stop. A particle at b_stop does nothing (the fixpoint).   */
 /* ------------------------------------------------------------------------- */
+/* Particle i's blocks for this round, drawing from the stream of slot `slot`. */
+static void propagate_one(or_run* r, uint64_t i, uint32_t slot)
+{
+    if (r->blk[i] == OR_STOP) return;
+    stream s = {r->seed, slot, r->round, OR_TAG_PROPAGATE, 0};
+    int b = r->blk[i];
+    for (;;) {
+        int ckpt = 0;
+        b = sim(r, i, b, &s, &ckpt);
+        r->block_steps += 1;
+        if (ckpt || b == (int)OR_STOP) break;
+    }
+    r->blk[i] = (uint8_t)b;
+}
+
 int32_t or_step(or_run* r)
 {
     if (r->status != OR_OK) return r->status;
-    for (uint64_t i = 0; i < r->n; ++i) {
-        if (r->blk[i] == OR_STOP) continue;
-        stream s = {r->seed, (uint32_t)i, r->round, OR_TAG_PROPAGATE, 0};
-        int b = r->blk[i];
-        for (;;) {
-            int ckpt = 0;
-            b = sim(r, i, b, &s, &ckpt);
-            r->block_steps += 1;
-            if (ckpt || b == (int)OR_STOP) break;
-        }
-        r->blk[i] = (uint8_t)b;
-    }
+    for (uint64_t i = 0; i < r->n; ++i) propagate_one(r, i, (uint32_t)i);
+    return OR_OK;
+}
+
+/* One particle's propagation in isolation (for checking sampled particles of a
+ * large run): the particle sits in slot `slot` of round `round` with the given
+ * block, state and zero log-weight. Real fields are read and written in FP64
+ * (already rounded to the storage precision); ints and the ClaDS stack follow
+ * the field order of or_read. */
+int32_t or_propagate_particle(const or_model* m, uint64_t seed, uint32_t slot, uint32_t round,
+                              uint8_t* blk, double* lw, double* reals, int32_t* ints, double* stack)
+{
+    or_run* r = or_create(m, 1, seed);
+    if (!r) return OR_ERR_INVALID;
+    r->round = round;
+    r->blk[0] = *blk;
+    for (int f = 0; f < r->n_real; ++f) r->real[f][0] = reals[f];
+    for (int f = 0; f < r->n_int; ++f) r->ints[f][0] = ints[f];
+    if (r->stack && stack) memcpy(r->stack, stack, (size_t)r->stack_depth * sizeof(double));
+    propagate_one(r, 0, slot);
+    *blk = r->blk[0];
+    *lw = r->lw[0];
+    for (int f = 0; f < r->n_real; ++f) reals[f] = r->real[f][0];
+    for (int f = 0; f < r->n_int; ++f) ints[f] = r->ints[f][0];
+    if (r->stack && stack) memcpy(stack, r->stack, (size_t)r->stack_depth * sizeof(double));
+    or_destroy(r);
     return OR_OK;
 }
 

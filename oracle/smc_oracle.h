@@ -77,6 +77,8 @@ uint32_t or_round(const or_run* r);
 uint64_t or_block_steps(const or_run* r);
 int32_t or_read(const or_run* r, int32_t what, void* dst);
 int32_t or_max_stack(const or_run* r);
+int32_t or_propagate_particle(const or_model* m, uint64_t seed, uint32_t slot, uint32_t round,
+                              uint8_t* blk, double* lw, double* reals, int32_t* ints, double* stack);
 
 /* or_read selectors */
 enum { OR_READ_BLK = 0, OR_READ_LW = 1, OR_READ_ANC = 2, OR_READ_FIELD0 = 16 };

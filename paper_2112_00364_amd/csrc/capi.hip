@@ -1,0 +1,760 @@
+// Host engine behind the C interface in include/pcfgsmc.h.
+//
+// The engine owns device memory (through the context's allocator), builds the
+// (run, tile) tables the kernels are launched over, enforces the call order of
+// Algorithm 1 (Sec. 3.2: propagation and resampling alternate) and turns the
+// device control block into status codes. Every kernel of a round reads the
+// round number and status from device memory, so the host never waits between
+// rounds; it synchronises only to answer a query.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pcfgsmc.h"
+
+#include "engine.hpp"
+#include "launch.hpp"
+
+using namespace pcfg;
+
+namespace {
+
+thread_local std::string g_error;
+
+smc_status fail(smc_status code, const std::string& msg)
+{
+    g_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(SMC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr uint64_t kMaxParticles = 1ull << 24;
+
+}  // namespace
+
+struct smc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    smc_allocator alloc{};
+    bool custom_alloc = false;
+
+    void* allocate(size_t bytes)
+    {
+        if (bytes == 0) bytes = 8;
+        if (custom_alloc) return alloc.alloc(alloc.ctx, bytes);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        return p;
+    }
+    void release(void* p)
+    {
+        if (!p) return;
+        if (custom_alloc) alloc.free(alloc.ctx, p);
+        else (void)hipFree(p);
+    }
+};
+
+namespace {
+
+// Device allocations owned by one object; released together.
+struct DeviceArena {
+    smc_ctx* ctx = nullptr;
+    std::vector<void*> ptrs;
+    void* get(size_t bytes)
+    {
+        void* p = ctx->allocate(bytes);
+        if (p) ptrs.push_back(p);
+        return p;
+    }
+    void release_all()
+    {
+        for (void* p : ptrs) ctx->release(p);
+        ptrs.clear();
+    }
+};
+
+int real_fields(int kind) { return kind == SMC_MODEL_LGSSM ? 1 : kind == SMC_MODEL_CRBD ? 2 : kind == SMC_MODEL_CLADS ? 4 : 0; }
+int stored_int_fields(int kind) { return kind == SMC_MODEL_GEOMETRIC ? 1 : 0; }
+// Int fields as the model defines them (some are the round, not stored).
+int logical_int_fields(int kind) { return kind == SMC_MODEL_CLADS ? 2 : 1; }
+
+}  // namespace
+
+struct smc_model {
+    smc_ctx* ctx = nullptr;
+    int kind = 0, precision = 64, checkpoint = 1, n_nodes = 0, T = 0;
+    int stack_depth = 0;
+    std::vector<int32_t> sp_before;  // ClaDS: stack size when node r is visited (index n_nodes = final)
+    ModelDev host{};
+    ModelDev* dev = nullptr;
+    DeviceArena arena;
+};
+
+struct smc_run {
+    smc_ctx* ctx = nullptr;
+    smc_model* model = nullptr;
+    uint64_t n = 0, seed = 0;
+    RunDev host{};
+    RunDev* dev = nullptr;
+    std::vector<TileRef> prop_tiles_h, red_tiles_h;
+    TileRef* prop_tiles = nullptr;
+    TileRef* red_tiles = nullptr;
+    uint32_t n_prop = 0, n_red = 0;
+    bool expect_step = true;   // Alg. 1: step 2 and step 3 alternate
+    uint32_t rounds_issued = 0;
+    int32_t known_status = SMC_OK;
+    DeviceArena arena;
+};
+
+namespace {
+
+smc_status read_ctl(smc_run* r, RunCtl* out)
+{
+    HIP_TRY(hipMemcpyAsync(out, r->host.ctl, sizeof(RunCtl), hipMemcpyDeviceToHost, r->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(r->ctx->stream));
+    if (out->status != SMC_OK) r->known_status = out->status;
+    return SMC_OK;
+}
+
+size_t real_bytes(const smc_model* m) { return m->precision == 32 ? 4 : 8; }
+
+// Allocate and initialise a run's device state (Alg. 1 step 1).
+smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
+{
+    smc_ctx* ctx = m->ctx;
+    r->ctx = ctx;
+    r->model = m;
+    r->n = n;
+    r->seed = seed;
+    r->arena.ctx = ctx;
+    RunDev& h = r->host;
+    h.seed = seed;
+    h.n = (uint32_t)n;
+    h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
+    h.model = m->dev;
+    const size_t rb = real_bytes(m);
+    auto get = [&](size_t bytes) { return r->arena.get(bytes); };
+    h.ctl = (RunCtl*)get(sizeof(RunCtl));
+    for (int b = 0; b < 2; ++b) {
+        h.buf[b].blk = (uint8_t*)get(n);
+        for (int f = 0; f < real_fields(m->kind); ++f) h.buf[b].real[f] = get(n * rb);
+        for (int f = 0; f < stored_int_fields(m->kind); ++f) h.buf[b].ints[f] = (int32_t*)get(n * 4);
+        if (m->kind == SMC_MODEL_CLADS) h.buf[b].stack = get(n * rb * (size_t)m->stack_depth);
+    }
+    h.lw = (double*)get(n * 8);
+    h.anc = (uint32_t*)get(n * 4);
+    h.part_q = (double*)get(h.red_tiles * 8);
+    h.part_e = (double*)get(h.red_tiles * 8);
+    h.prefix = (double*)get(h.red_tiles * 8);
+    r->dev = (RunDev*)get(sizeof(RunDev));
+    r->n_prop = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
+    r->n_red = h.red_tiles;
+    r->prop_tiles = (TileRef*)get(sizeof(TileRef) * r->n_prop);
+    r->red_tiles = (TileRef*)get(sizeof(TileRef) * r->n_red);
+    bool ok = h.ctl && h.lw && h.anc && h.part_q && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
+    for (int b = 0; b < 2; ++b) {
+        ok = ok && h.buf[b].blk;
+        for (int f = 0; f < real_fields(m->kind); ++f) ok = ok && h.buf[b].real[f];
+        for (int f = 0; f < stored_int_fields(m->kind); ++f) ok = ok && h.buf[b].ints[f];
+        if (m->kind == SMC_MODEL_CLADS) ok = ok && h.buf[b].stack;
+    }
+    if (!ok) {
+        r->arena.release_all();
+        return fail(SMC_ERR_OOM, "device allocation failed for a run of " + std::to_string(n) + " particles");
+    }
+    r->prop_tiles_h.resize(r->n_prop);
+    r->red_tiles_h.resize(r->n_red);
+    for (uint32_t t = 0; t < r->n_prop; ++t) r->prop_tiles_h[t] = TileRef{0, t};
+    for (uint32_t t = 0; t < r->n_red; ++t) r->red_tiles_h[t] = TileRef{0, t};
+    hipStream_t st = ctx->stream;
+    HIP_TRY(hipMemsetAsync(h.ctl, 0, sizeof(RunCtl), st));
+    HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(r->prop_tiles, r->prop_tiles_h.data(), sizeof(TileRef) * r->n_prop,
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(r->red_tiles, r->red_tiles_h.data(), sizeof(TileRef) * r->n_red,
+                           hipMemcpyHostToDevice, st));
+    // the host copies above live in the run object until it is destroyed
+    return SMC_OK;
+}
+
+smc_status do_step(smc_run* r)
+{
+    if (!r->expect_step) return fail(SMC_ERR_STATE, "smc_step called twice without smc_resample");
+    if (r->known_status != SMC_OK) return r->known_status;
+    HIP_TRY(launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, r->ctx->stream));
+    r->expect_step = false;
+    return SMC_OK;
+}
+
+smc_status do_resample(smc_run* r)
+{
+    if (r->expect_step) return fail(SMC_ERR_STATE, "smc_resample called before smc_step");
+    if (r->known_status != SMC_OK) return r->known_status;
+    HIP_TRY(launch_resample(r->dev, r->red_tiles, r->n_red, r->ctx->stream));
+    r->expect_step = true;
+    r->rounds_issued += 1;
+    return SMC_OK;
+}
+
+// Rounds a model needs when every particle advances in lockstep (0 = unknown).
+uint32_t lockstep_rounds(const smc_model* m)
+{
+    if (m->kind == SMC_MODEL_LGSSM) return (uint32_t)m->T;
+    if (m->kind == SMC_MODEL_CRBD || m->kind == SMC_MODEL_CLADS) return (uint32_t)m->n_nodes;
+    return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C interface
+// ===========================================================================
+extern "C" {
+
+const char* smc_last_error(void) { return g_error.c_str(); }
+const char* smc_version(void) { return "pcfgsmc 0.1 gfx950"; }
+
+smc_status smc_ctx_create(int32_t device, void* stream, const smc_allocator* allocator, smc_ctx** out)
+{
+    if (!out) return fail(SMC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (allocator && (!allocator->alloc || !allocator->free))
+        return fail(SMC_ERR_INVALID, "allocator needs both alloc and free");
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(SMC_ERR_INVALID, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    smc_ctx* c = new (std::nothrow) smc_ctx();
+    if (!c) return fail(SMC_ERR_OOM, "host allocation failed");
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (allocator) {
+        c->alloc = *allocator;
+        c->custom_alloc = true;
+    }
+    *out = c;
+    return SMC_OK;
+}
+
+smc_status smc_ctx_destroy(smc_ctx* ctx)
+{
+    delete ctx;
+    return SMC_OK;
+}
+
+smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model** out)
+{
+    if (!ctx || !d || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (d->kind < SMC_MODEL_GEOMETRIC || d->kind > SMC_MODEL_CLADS) return fail(SMC_ERR_INVALID, "unknown model kind");
+    if (d->precision != 32 && d->precision != 64) return fail(SMC_ERR_INVALID, "precision must be 32 or 64");
+    const bool tree = d->kind == SMC_MODEL_CRBD || d->kind == SMC_MODEL_CLADS;
+    if (tree) {
+        if (d->n_nodes < 1 || d->n_nodes > 1 << 20 || !d->parent || !d->left || !d->age)
+            return fail(SMC_ERR_INVALID, "tree arrays missing or empty");
+        if (d->parent[0] != -1) return fail(SMC_ERR_INVALID, "node 0 must be the root");
+        for (int i = 1; i < d->n_nodes; ++i)
+            if (d->parent[i] < 0 || d->parent[i] >= i || !(d->age[d->parent[i]] >= d->age[i]))
+                return fail(SMC_ERR_INVALID, "tree is not in preorder with ages decreasing from the root");
+        const int ev = d->kind == SMC_MODEL_CRBD ? 5 : 7;
+        if (!(d->params[ev + 1] >= 1.0 && d->params[ev + 1] <= 32.0))
+            return fail(SMC_ERR_INVALID, "max depth must be in [1, 32]");
+        if (!(d->params[ev] >= 0.0 && d->params[ev] <= 1e6)) return fail(SMC_ERR_INVALID, "max events must be in [0, 10^6]");
+        if (!(d->params[0] > 0.0 && d->params[0] <= 1.0)) return fail(SMC_ERR_INVALID, "rho must be in (0, 1]");
+    }
+    if (d->kind == SMC_MODEL_LGSSM && (d->T < 1 || d->T > (1 << 24) || !d->y))
+        return fail(SMC_ERR_INVALID, "observations missing");
+    smc_model* m = new (std::nothrow) smc_model();
+    if (!m) return fail(SMC_ERR_OOM, "host allocation failed");
+    m->ctx = ctx;
+    m->arena.ctx = ctx;
+    m->kind = d->kind;
+    m->precision = d->precision;
+    m->checkpoint = d->checkpoint;
+    m->n_nodes = tree ? d->n_nodes : 0;
+    m->T = d->kind == SMC_MODEL_LGSSM ? d->T : 0;
+    ModelDev& h = m->host;
+    h.kind = d->kind;
+    h.precision = d->precision;
+    h.checkpoint = d->checkpoint;
+    h.n_nodes = m->n_nodes;
+    h.T = m->T;
+    for (int i = 0; i < 16; ++i) h.p[i] = d->params[i];
+    hipStream_t st = ctx->stream;
+    auto upload = [&](const void* src, size_t bytes) -> void* {
+        void* p = m->arena.get(bytes);
+        if (p && hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return nullptr;
+        return p;
+    };
+    bool ok = true;
+    if (tree) {
+        h.parent = (const int32_t*)upload(d->parent, sizeof(int32_t) * d->n_nodes);
+        h.left = (const int32_t*)upload(d->left, sizeof(int32_t) * d->n_nodes);
+        h.age = (const double*)upload(d->age, sizeof(double) * d->n_nodes);
+        ok = h.parent && h.left && h.age;
+        if (d->kind == SMC_MODEL_CLADS) {
+            // pending right daughters along the preorder walk (same for every particle)
+            m->sp_before.assign(d->n_nodes + 1, 0);
+            int cur = 1, deepest = 1;
+            for (int node = 1; node < d->n_nodes; ++node) {
+                m->sp_before[node] = cur;
+                cur = d->left[node] >= 0 ? cur + 1 : (cur > 0 ? cur - 1 : 0);
+                if (cur > deepest) deepest = cur;
+            }
+            m->sp_before[d->n_nodes] = cur;
+            m->stack_depth = deepest + 1;
+            h.stack_depth = m->stack_depth;
+            h.sp_before = (const int32_t*)upload(m->sp_before.data(), sizeof(int32_t) * m->sp_before.size());
+            ok = ok && h.sp_before;
+        }
+    }
+    if (d->kind == SMC_MODEL_LGSSM) {
+        h.y = (const double*)upload(d->y, sizeof(double) * d->T);
+        ok = ok && h.y;
+    }
+    m->dev = (ModelDev*)m->arena.get(sizeof(ModelDev));
+    ok = ok && m->dev;
+    if (!ok) {
+        (void)hipStreamSynchronize(st);
+        m->arena.release_all();
+        delete m;
+        return fail(SMC_ERR_OOM, "device allocation failed for model data");
+    }
+    if (hipMemcpyAsync(m->dev, &m->host, sizeof(ModelDev), hipMemcpyHostToDevice, st) != hipSuccess ||
+        launch_model_setup(m->dev, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        m->arena.release_all();
+        delete m;
+        return fail(SMC_ERR_DEVICE, "model upload failed");
+    }
+    *out = m;
+    return SMC_OK;
+}
+
+smc_status smc_model_destroy(smc_model* m)
+{
+    if (!m) return SMC_OK;
+    (void)hipStreamSynchronize(m->ctx->stream);
+    m->arena.release_all();
+    delete m;
+    return SMC_OK;
+}
+
+smc_status smc_init(smc_model* model, uint64_t n, uint64_t seed, smc_run** out)
+{
+    if (!model || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (n == 0 || n > kMaxParticles) return fail(SMC_ERR_INVALID, "particle count must be in [1, 2^24]");
+    smc_run* r = new (std::nothrow) smc_run();
+    if (!r) return fail(SMC_ERR_OOM, "host allocation failed");
+    smc_status s = build_run(model, n, seed, r);
+    if (s != SMC_OK) {
+        delete r;
+        return s;
+    }
+    *out = r;
+    return SMC_OK;
+}
+
+smc_status smc_step(smc_run* r)
+{
+    if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    return do_step(r);
+}
+
+smc_status smc_resample(smc_run* r)
+{
+    if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    return do_resample(r);
+}
+
+smc_status smc_done(smc_run* r, int32_t* done)
+{
+    if (!r || !done) return fail(SMC_ERR_INVALID, "NULL argument");
+    RunCtl c;
+    smc_status s = read_ctl(r, &c);
+    if (s != SMC_OK) return s;
+    *done = c.status != SMC_OK;
+    return c.status;
+}
+
+smc_status smc_log_z(smc_run* r, double* out)
+{
+    if (!r || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    RunCtl c;
+    smc_status s = read_ctl(r, &c);
+    if (s != SMC_OK) return s;
+    *out = c.log_z;
+    return c.status;
+}
+
+smc_status smc_run_to_end(smc_run* r)
+{
+    if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    if (!r->expect_step) {
+        smc_status s = do_resample(r);
+        if (s != SMC_OK) return s;
+    }
+    const uint32_t known = lockstep_rounds(r->model);
+    uint32_t chunk = 16;
+    if (known && r->rounds_issued < known) chunk = known - r->rounds_issued;
+    for (;;) {
+        for (uint32_t k = 0; k < chunk; ++k) {
+            smc_status s = do_step(r);
+            if (s != SMC_OK) return s;
+            s = do_resample(r);
+            if (s != SMC_OK) return s;
+        }
+        RunCtl c;
+        smc_status s = read_ctl(r, &c);
+        if (s != SMC_OK) return s;
+        if (c.status != SMC_OK) return c.status;
+        chunk = 16;
+    }
+}
+
+smc_status smc_read(smc_run* r, int32_t what, void* dst, size_t bytes)
+{
+    if (!r || !dst) return fail(SMC_ERR_INVALID, "NULL argument");
+    RunCtl c;
+    smc_status s = read_ctl(r, &c);
+    if (s != SMC_OK) return s;
+    const smc_model* m = r->model;
+    const uint64_t n = r->n;
+    hipStream_t st = r->ctx->stream;
+    if (r->rounds_issued == 0 && r->expect_step) return fail(SMC_ERR_STATE, "nothing propagated yet");
+    // Where the newest state lives, and whether it still waits for its gather.
+    const bool pending_gather = r->expect_step && c.status == SMC_OK;
+    const uint32_t last_round = pending_gather ? c.round - 1 : c.round;
+    const ParticleBuf& b = r->host.buf[last_round & 1u];
+    const uint32_t* anc = pending_gather ? r->host.anc : nullptr;
+    auto fetch = [&](const void* src, int elem, uint64_t levels) -> smc_status {
+        const size_t need = (size_t)elem * n * levels;
+        if (bytes < need) return fail(SMC_ERR_INVALID, "destination too small");
+        void* tmp = r->ctx->allocate(need);
+        if (!tmp) return fail(SMC_ERR_OOM, "temporary allocation failed");
+        hipError_t e = launch_gather(elem, src, anc, tmp, n, levels, n, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst, tmp, need, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        r->ctx->release(tmp);
+        if (e != hipSuccess) return fail(SMC_ERR_DEVICE, hipGetErrorString(e));
+        return SMC_OK;
+    };
+    if (what == SMC_READ_BLK) return fetch(b.blk, 1, 1);
+    if (what == SMC_READ_LW) {
+        if (bytes < n * 8) return fail(SMC_ERR_INVALID, "destination too small");
+        if (pending_gather) {
+            std::memset(dst, 0, n * 8);  // weights are reset by resampling
+            return SMC_OK;
+        }
+        HIP_TRY(hipMemcpyAsync(dst, r->host.lw, n * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return SMC_OK;
+    }
+    if (what == SMC_READ_ANC) {
+        if (bytes < n * 4) return fail(SMC_ERR_INVALID, "destination too small");
+        HIP_TRY(hipMemcpyAsync(dst, r->host.anc, n * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return SMC_OK;
+    }
+    int f = what - SMC_READ_FIELD0;
+    const int nr = real_fields(m->kind);
+    const int elem = (int)real_bytes(m);
+    if (f >= 0 && f < nr) return fetch(b.real[f], elem, 1);
+    f -= nr;
+    if (f >= 0 && f < logical_int_fields(m->kind)) {
+        if (bytes < n * 4) return fail(SMC_ERR_INVALID, "destination too small");
+        if (m->kind == SMC_MODEL_GEOMETRIC) return fetch(b.ints[0], 4, 1);
+        // cursor-like fields advance once per round for every particle
+        int32_t v = (int32_t)last_round + 1;
+        if (m->kind == SMC_MODEL_CLADS && f == 1) {
+            const int node = (int)last_round;
+            if (node == 0) v = 1;
+            else v = m->sp_before[node + 1 <= m->n_nodes ? node + 1 : m->n_nodes];
+        }
+        int32_t* o = (int32_t*)dst;
+        for (uint64_t i = 0; i < n; ++i) o[i] = v;
+        return SMC_OK;
+    }
+    f -= logical_int_fields(m->kind);
+    if (f == 0 && m->kind == SMC_MODEL_CLADS) {
+        const uint64_t depth = (uint64_t)m->stack_depth;
+        const size_t need = (size_t)elem * n * depth;
+        if (bytes < need) return fail(SMC_ERR_INVALID, "destination too small");
+        std::vector<char> level_major(need);
+        s = fetch(b.stack, elem, depth);
+        if (s != SMC_OK) return s;
+        // fetch wrote level-major into dst; transpose to [particle][level]
+        std::memcpy(level_major.data(), dst, need);
+        char* o = (char*)dst;
+        for (uint64_t i = 0; i < n; ++i)
+            for (uint64_t k = 0; k < depth; ++k)
+                std::memcpy(o + (i * depth + k) * elem, level_major.data() + (k * n + i) * elem, elem);
+        return SMC_OK;
+    }
+    return fail(SMC_ERR_INVALID, "unknown read selector");
+}
+
+smc_status smc_run_stats(smc_run* r, smc_stats* out)
+{
+    if (!r || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    RunCtl c;
+    smc_status s = read_ctl(r, &c);
+    if (s != SMC_OK) return s;
+    out->round = c.round;
+    out->status = c.status;
+    out->block_steps = c.block_steps;
+    out->log_z = c.log_z;
+    out->stack_depth = r->model->stack_depth;
+    return SMC_OK;
+}
+
+smc_status smc_run_destroy(smc_run* r)
+{
+    if (!r) return SMC_OK;
+    (void)hipStreamSynchronize(r->ctx->stream);
+    r->arena.release_all();
+    delete r;
+    return SMC_OK;
+}
+
+smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint64_t seed, uint32_t round,
+                                uint32_t* anc, double* logz_inc)
+{
+    if (!ctx || !lw || !anc || !logz_inc) return fail(SMC_ERR_INVALID, "NULL argument");
+    if (n == 0 || n > kMaxParticles) return fail(SMC_ERR_INVALID, "n must be in [1, 2^24]");
+    DeviceArena arena;
+    arena.ctx = ctx;
+    RunDev h{};
+    h.seed = seed;
+    h.n = (uint32_t)n;
+    h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
+    h.lw = const_cast<double*>(lw);
+    h.anc = anc;
+    h.ctl = (RunCtl*)arena.get(sizeof(RunCtl));
+    h.part_q = (double*)arena.get(h.red_tiles * 8);
+    h.part_e = (double*)arena.get(h.red_tiles * 8);
+    h.prefix = (double*)arena.get(h.red_tiles * 8);
+    RunDev* dev = (RunDev*)arena.get(sizeof(RunDev));
+    TileRef* tiles = (TileRef*)arena.get(sizeof(TileRef) * h.red_tiles);
+    if (!h.ctl || !h.part_q || !h.part_e || !h.prefix || !dev || !tiles) {
+        arena.release_all();
+        return fail(SMC_ERR_OOM, "device allocation failed");
+    }
+    std::vector<TileRef> th(h.red_tiles);
+    for (uint32_t t = 0; t < h.red_tiles; ++t) th[t] = TileRef{0, t};
+    RunCtl c0{};
+    c0.round = round;
+    hipStream_t st = ctx->stream;
+    hipError_t e = hipMemcpyAsync(h.ctl, &c0, sizeof(RunCtl), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(dev, &h, sizeof(RunDev), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(tiles, th.data(), sizeof(TileRef) * th.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_maxkey(dev, tiles, h.red_tiles, st);
+    if (e == hipSuccess) e = launch_resample(dev, tiles, h.red_tiles, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(logz_inc, &h.ctl->log_z, sizeof(double), hipMemcpyDeviceToDevice, st);
+    RunCtl c{};
+    if (e == hipSuccess) e = hipMemcpyAsync(&c, h.ctl, sizeof(RunCtl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    arena.release_all();
+    if (e != hipSuccess) return fail(SMC_ERR_DEVICE, hipGetErrorString(e));
+    return c.status;
+}
+
+// ---------------------------------------------------------------------------
+// Batches: the same round kernels over a combined (run, tile) table.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct smc_batch {
+    smc_ctx* ctx = nullptr;
+    std::vector<smc_run*> slots;  // nullptr = free slot
+    bool dirty = true;
+    DeviceArena tables;
+    RunDev* runs = nullptr;
+    struct Group {
+        int kind, precision;
+        TileRef* tiles;
+        uint32_t n;
+    };
+    std::vector<Group> groups;
+    TileRef* red_tiles = nullptr;
+    uint32_t n_red = 0;
+    std::vector<RunDev> runs_h;
+    std::vector<std::vector<TileRef>> group_tiles_h;
+    std::vector<TileRef> red_tiles_h;
+};
+
+namespace {
+
+smc_status rebuild_tables(smc_batch* b)
+{
+    hipStream_t st = b->ctx->stream;
+    HIP_TRY(hipStreamSynchronize(st));  // old tables may still be in use
+    b->tables.release_all();
+    b->groups.clear();
+    b->runs_h.clear();
+    b->group_tiles_h.clear();
+    b->red_tiles_h.clear();
+    struct Key {
+        int kind, precision;
+    };
+    std::vector<Key> keys;
+    for (smc_run* r : b->slots) {
+        if (!r) continue;
+        const uint32_t idx = (uint32_t)b->runs_h.size();
+        b->runs_h.push_back(r->host);
+        size_t g = 0;
+        for (; g < keys.size(); ++g)
+            if (keys[g].kind == r->model->kind && keys[g].precision == r->model->precision) break;
+        if (g == keys.size()) {
+            keys.push_back(Key{r->model->kind, r->model->precision});
+            b->group_tiles_h.emplace_back();
+        }
+        for (uint32_t t = 0; t < r->n_prop; ++t) b->group_tiles_h[g].push_back(TileRef{idx, t});
+        for (uint32_t t = 0; t < r->n_red; ++t) b->red_tiles_h.push_back(TileRef{idx, t});
+    }
+    b->dirty = false;
+    if (b->runs_h.empty()) return SMC_OK;
+    b->runs = (RunDev*)b->tables.get(sizeof(RunDev) * b->runs_h.size());
+    b->red_tiles = (TileRef*)b->tables.get(sizeof(TileRef) * b->red_tiles_h.size());
+    if (!b->runs || !b->red_tiles) return fail(SMC_ERR_OOM, "batch table allocation failed");
+    HIP_TRY(hipMemcpyAsync(b->runs, b->runs_h.data(), sizeof(RunDev) * b->runs_h.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(b->red_tiles, b->red_tiles_h.data(), sizeof(TileRef) * b->red_tiles_h.size(),
+                           hipMemcpyHostToDevice, st));
+    b->n_red = (uint32_t)b->red_tiles_h.size();
+    for (size_t g = 0; g < keys.size(); ++g) {
+        TileRef* t = (TileRef*)b->tables.get(sizeof(TileRef) * b->group_tiles_h[g].size());
+        if (!t) return fail(SMC_ERR_OOM, "batch table allocation failed");
+        HIP_TRY(hipMemcpyAsync(t, b->group_tiles_h[g].data(), sizeof(TileRef) * b->group_tiles_h[g].size(),
+                               hipMemcpyHostToDevice, st));
+        b->groups.push_back(smc_batch::Group{keys[g].kind, keys[g].precision, t, (uint32_t)b->group_tiles_h[g].size()});
+    }
+    return SMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+smc_status smc_batch_create(smc_ctx* ctx, smc_batch** out)
+{
+    if (!ctx || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    smc_batch* b = new (std::nothrow) smc_batch();
+    if (!b) return fail(SMC_ERR_OOM, "host allocation failed");
+    b->ctx = ctx;
+    b->tables.ctx = ctx;
+    *out = b;
+    return SMC_OK;
+}
+
+smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n, uint64_t seed, int32_t* slot)
+{
+    if (!b || !model || !slot) return fail(SMC_ERR_INVALID, "NULL argument");
+    if (model->ctx != b->ctx) return fail(SMC_ERR_INVALID, "model belongs to another context");
+    smc_run* r = nullptr;
+    smc_status s = smc_init(model, n, seed, &r);
+    if (s != SMC_OK) return s;
+    int32_t idx = -1;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (!b->slots[i]) {
+            idx = (int32_t)i;
+            break;
+        }
+    if (idx < 0) {
+        idx = (int32_t)b->slots.size();
+        b->slots.push_back(nullptr);
+    }
+    b->slots[idx] = r;
+    b->dirty = true;
+    *slot = idx;
+    return SMC_OK;
+}
+
+smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
+{
+    if (!b || rounds < 0) return fail(SMC_ERR_INVALID, "bad argument");
+    if (b->dirty) {
+        smc_status s = rebuild_tables(b);
+        if (s != SMC_OK) return s;
+    }
+    if (b->runs_h.empty()) return SMC_OK;
+    hipStream_t st = b->ctx->stream;
+    for (int32_t k = 0; k < rounds; ++k) {
+        for (const auto& g : b->groups) HIP_TRY(launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, st));
+        HIP_TRY(launch_resample(b->runs, b->red_tiles, b->n_red, st));
+    }
+    for (smc_run* r : b->slots)
+        if (r) r->rounds_issued += (uint32_t)rounds;
+    return SMC_OK;
+}
+
+smc_status smc_batch_poll(smc_batch* b, int32_t slots, int32_t* done, double* log_z, int32_t* status,
+                          uint64_t* block_steps)
+{
+    if (!b || slots < 0) return fail(SMC_ERR_INVALID, "bad argument");
+    const int32_t m = slots < (int32_t)b->slots.size() ? slots : (int32_t)b->slots.size();
+    std::vector<RunCtl> c(m);
+    hipStream_t st = b->ctx->stream;
+    for (int32_t i = 0; i < m; ++i)
+        if (b->slots[i]) HIP_TRY(hipMemcpyAsync(&c[i], b->slots[i]->host.ctl, sizeof(RunCtl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int32_t i = 0; i < slots; ++i) {
+        const bool live = i < m && b->slots[i];
+        if (done) done[i] = live ? (c[i].status != SMC_OK) : 1;
+        if (log_z) log_z[i] = live ? c[i].log_z : 0.0;
+        if (status) status[i] = live ? c[i].status : SMC_ERR_STATE;
+        if (block_steps) block_steps[i] = live ? c[i].block_steps : 0;
+    }
+    return SMC_OK;
+}
+
+smc_status smc_batch_retire(smc_batch* b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= (int32_t)b->slots.size() || !b->slots[slot])
+        return fail(SMC_ERR_INVALID, "no such slot");
+    smc_run_destroy(b->slots[slot]);
+    b->slots[slot] = nullptr;
+    b->dirty = true;
+    return SMC_OK;
+}
+
+smc_status smc_batch_destroy(smc_batch* b)
+{
+    if (!b) return SMC_OK;
+    (void)hipStreamSynchronize(b->ctx->stream);
+    for (smc_run* r : b->slots) smc_run_destroy(r);
+    b->tables.release_all();
+    delete b;
+    return SMC_OK;
+}
+
+smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n)
+{
+    if (!ctx || !in || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    if (op < 0 || op > 6) return fail(SMC_ERR_INVALID, "unknown op");
+    if (n == 0) return SMC_OK;
+    HIP_TRY(launch_selftest_math(op, in, out, n, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SMC_OK;
+}
+
+smc_status smc_selftest_philox(smc_ctx* ctx, const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n)
+{
+    if (!ctx || !ctr || !key || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    if (n == 0) return SMC_OK;
+    HIP_TRY(launch_selftest_philox(ctr, key, out, n, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SMC_OK;
+}
+
+}  // extern "C"

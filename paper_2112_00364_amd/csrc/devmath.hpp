@@ -1,0 +1,268 @@
+// Device primitives for the particle blocks: counter-based random words,
+// uniforms, the pinned FP64 elementary functions and the samplers.
+//
+// Every function here rounds exactly once per written operation (the library
+// is compiled with -ffp-contract=off; fused multiply-adds are explicit), so a
+// block computes the same bits wherever it runs. The pinned algorithms are the
+// library's reading of what the paper leaves open: the paper's engine draws
+// per-thread random numbers (Sec. 3.3) and its listings use exp, log,
+// Exponential, Poisson, Uniform, Bernoulli and Gamma draws (Appendix B).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcfg {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__host__ __device__ inline Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
+enum : uint32_t { kTagPropagate = 0, kTagResample = 1 };
+
+// One particle's words for one round, drawn in program order. Word k is lane
+// k%4 of the Philox block with counter {k/4, particle, round, tag}.
+struct Stream {
+    uint32_t key0, key1, particle, round, tag;
+    uint32_t k;
+    Words4 buf;
+
+    __device__ inline void start(uint64_t seed, uint32_t p, uint32_t r, uint32_t t)
+    {
+        key0 = (uint32_t)seed;
+        key1 = (uint32_t)(seed >> 32);
+        particle = p;
+        round = r;
+        tag = t;
+        k = 0;
+    }
+
+    __device__ inline uint32_t next()
+    {
+        const uint32_t lane = k & 3u;
+        if (lane == 0u) buf = philox10(k >> 2, particle, round, tag, key0, key1);
+        k += 1u;
+        uint32_t w = buf.w3;
+        w = (lane == 0u) ? buf.w0 : w;
+        w = (lane == 1u) ? buf.w1 : w;
+        w = (lane == 2u) ? buf.w2 : w;
+        return w;
+    }
+
+    __device__ inline double uniform() { return word_to_uniform(next()); }
+
+    __host__ __device__ static inline double word_to_uniform(uint32_t w)
+    {
+        // (2w + 1) 2^-33: exact, strictly inside (0, 1)
+        return ((double)w * 2.0 + 1.0) * 0x1p-33;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Pinned FP64 elementary functions.
+// ---------------------------------------------------------------------------
+namespace fn {
+
+// ln 2 split as a 24-bit head (exact products with small integers) and tail.
+constexpr double kLn2Head = 0.693147182464599609375;
+constexpr double kLn2Tail = -1.904654299957767878541823431924e-9;
+constexpr double kLog2e = 1.442695040888963407359924681001892137427;
+constexpr double kRoot2 = 1.41421356237309504880168872420969807857;
+constexpr double kTau = 6.283185307179586476925286766559005768394;   // 2 pi
+
+__device__ inline double two_to(int n)   // 2^n, -1022 <= n <= 1023
+{
+    return __longlong_as_double((long long)(n + 1023) << 52);
+}
+
+// exp: x = n ln2 + r with n = rint(x log2 e) and r reduced in two steps
+// (head, tail); e^r from its degree-13 Taylor polynomial (Horner, fma);
+// result scaled by 2^n. Below -708 the result is flushed to +0, above 709 it
+// is +inf.
+__device__ inline double exp(double x)
+{
+    if (x != x) return x;
+    if (x > 709.0) return __builtin_huge_val();
+    if (x < -708.0) return 0.0;
+    const double n = __builtin_rint(x * kLog2e);
+    const double r = (x - n * kLn2Head) - n * kLn2Tail;
+    double p = 1.0 / 6227020800.0;
+    p = __builtin_fma(p, r, 1.0 / 479001600.0);
+    p = __builtin_fma(p, r, 1.0 / 39916800.0);
+    p = __builtin_fma(p, r, 1.0 / 3628800.0);
+    p = __builtin_fma(p, r, 1.0 / 362880.0);
+    p = __builtin_fma(p, r, 1.0 / 40320.0);
+    p = __builtin_fma(p, r, 1.0 / 5040.0);
+    p = __builtin_fma(p, r, 1.0 / 720.0);
+    p = __builtin_fma(p, r, 1.0 / 120.0);
+    p = __builtin_fma(p, r, 1.0 / 24.0);
+    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = __builtin_fma(p, r, 0.5);
+    p = __builtin_fma(p, r, 1.0);
+    p = __builtin_fma(p, r, 1.0);
+    return p * two_to((int)n);
+}
+
+// log: x = 2^k m, m in [sqrt(2)/2, sqrt(2)); with f = m - 1 and s = f / (2 + f),
+// log m = 2 atanh s = 2s + 2s * z * R(z), z = s^2, R(z) = sum_{j<10} z^j / (2j + 3);
+// log x = k ln2_head + (k ln2_tail + log m).
+__device__ inline double log(double x)
+{
+    if (x != x) return x;
+    if (x < 0.0) return __builtin_nan("");
+    if (x == 0.0) return -__builtin_huge_val();
+    if (x == __builtin_huge_val()) return x;
+    int k = 0;
+    if (x < 0x1p-1022) {
+        x = x * 0x1p54;
+        k = -54;
+    }
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+    k += (int)((bits >> 52) & 0x7ffull) - 1023;
+    double m = __longlong_as_double((long long)((bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+    if (m > kRoot2) {
+        m = m * 0.5;
+        k += 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double R = 1.0 / 21.0;
+    R = __builtin_fma(R, z, 1.0 / 19.0);
+    R = __builtin_fma(R, z, 1.0 / 17.0);
+    R = __builtin_fma(R, z, 1.0 / 15.0);
+    R = __builtin_fma(R, z, 1.0 / 13.0);
+    R = __builtin_fma(R, z, 1.0 / 11.0);
+    R = __builtin_fma(R, z, 1.0 / 9.0);
+    R = __builtin_fma(R, z, 1.0 / 7.0);
+    R = __builtin_fma(R, z, 1.0 / 5.0);
+    R = __builtin_fma(R, z, 1.0 / 3.0);
+    const double s2 = 2.0 * s;
+    const double log_m = __builtin_fma(s2, z * R, s2);
+    const double kd = (double)k;
+    return kd * kLn2Head + (kd * kLn2Tail + log_m);
+}
+
+// cos(2 pi u): quadrant q = rint(4u); t = u - q/4 (exact) in [-1/8, 1/8];
+// theta = 2 pi t; sin and cos of theta from their Taylor series in theta^2.
+__device__ inline double cos2pi(double u)
+{
+    const double q = __builtin_rint(4.0 * u);
+    const double t = u - q * 0.25;
+    const double th = t * kTau;
+    const double z = th * th;
+    double S = 1.0 / 355687428096000.0;
+    S = __builtin_fma(S, z, -1.0 / 1307674368000.0);
+    S = __builtin_fma(S, z, 1.0 / 6227020800.0);
+    S = __builtin_fma(S, z, -1.0 / 39916800.0);
+    S = __builtin_fma(S, z, 1.0 / 362880.0);
+    S = __builtin_fma(S, z, -1.0 / 5040.0);
+    S = __builtin_fma(S, z, 1.0 / 120.0);
+    S = __builtin_fma(S, z, -1.0 / 6.0);
+    S = __builtin_fma(S, z, 1.0);
+    const double sn = th * S;
+    double C = -1.0 / 6402373705728000.0;
+    C = __builtin_fma(C, z, 1.0 / 20922789888000.0);
+    C = __builtin_fma(C, z, -1.0 / 87178291200.0);
+    C = __builtin_fma(C, z, 1.0 / 479001600.0);
+    C = __builtin_fma(C, z, -1.0 / 3628800.0);
+    C = __builtin_fma(C, z, 1.0 / 40320.0);
+    C = __builtin_fma(C, z, -1.0 / 720.0);
+    C = __builtin_fma(C, z, 1.0 / 24.0);
+    C = __builtin_fma(C, z, -0.5);
+    C = __builtin_fma(C, z, 1.0);
+    const int quadrant = ((int)q) & 3;
+    double out = C;
+    out = (quadrant == 1) ? -sn : out;
+    out = (quadrant == 2) ? -C : out;
+    out = (quadrant == 3) ? sn : out;
+    return out;
+}
+
+// Correctly rounded square root.
+__device__ inline double sqrt(double x) { return __builtin_sqrt(x); }
+
+constexpr double kEventCap = 10000.0;
+constexpr int kMaxInversionSteps = 10000;
+
+}  // namespace fn
+
+// ---------------------------------------------------------------------------
+// Samplers.
+// ---------------------------------------------------------------------------
+__device__ inline double draw_exponential(Stream& s, double rate) { return -fn::log(s.uniform()) / rate; }
+__device__ inline double draw_gamma1(Stream& s, double scale) { return -scale * fn::log(s.uniform()); }
+__device__ inline double draw_uniform(Stream& s, double a, double b) { return a + (b - a) * s.uniform(); }
+__device__ inline bool draw_bernoulli(Stream& s, double p) { return s.uniform() < p; }
+
+// Box-Muller, cosine branch: sqrt(-2 log u1) cos(2 pi u2).
+__device__ inline double normal_from(double u1, double u2)
+{
+    const double radius = fn::sqrt(-2.0 * fn::log(u1));
+    return radius * fn::cos2pi(u2);
+}
+
+__device__ inline double draw_normal(Stream& s)
+{
+    const double u1 = s.uniform();
+    const double u2 = s.uniform();
+    return normal_from(u1, u2);
+}
+
+__device__ inline double draw_lognormal(Stream& s, double mu_ln, double sigma)
+{
+    const double z = draw_normal(s);
+    return fn::exp(mu_ln + sigma * z);
+}
+
+// Poisson(m): inversion of the CDF, with m split into ceil(m/32) equal chunks
+// (one uniform per chunk; the chunk counts add up). Returns -1 when m exceeds
+// the event cap or is not a number.
+__device__ inline int draw_poisson(Stream& s, double m)
+{
+    if (!(m >= 0.0) || m > fn::kEventCap) return -1;
+    if (m == 0.0) return 0;
+    const int chunks = (int)__builtin_ceil(m / 32.0);
+    const double mc = m / (double)chunks;
+    const double p0 = fn::exp(-mc);
+    int total = 0;
+    for (int c = 0; c < chunks; ++c) {
+        const double u = s.uniform();
+        double p = p0;
+        double F = p;
+        int k = 0;
+        while (u > F && k < fn::kMaxInversionSteps) {
+            k += 1;
+            p = p * mc / (double)k;
+            F = F + p;
+        }
+        total += k;
+    }
+    return total;
+}
+
+}  // namespace pcfg

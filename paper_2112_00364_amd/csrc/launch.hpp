@@ -1,0 +1,21 @@
+// Kernel launchers (defined in kernels.hip, used by the host engine).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "engine.hpp"
+
+namespace pcfg {
+
+hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const TileRef* tiles, uint32_t n_tiles,
+                            hipStream_t st);
+hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
+hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
+hipError_t launch_gather(int elem_bytes, const void* src, const uint32_t* anc, void* dst, uint64_t n,
+                         uint64_t levels, uint64_t stride, hipStream_t st);
+hipError_t launch_selftest_math(int op, const double* in, double* out, uint64_t n, hipStream_t st);
+hipError_t launch_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n,
+                                  hipStream_t st);
+hipError_t launch_model_setup(ModelDev* m, hipStream_t st);
+
+}  // namespace pcfg

@@ -1,0 +1,336 @@
+// Built-in PCFG block tables (Sec. 3.1): for each model, the blocks B, the
+// per-particle state S (held in registers while a block runs) and sim, which
+// runs one block and returns the successor plus whether a checkpoint follows.
+//
+// All tree/observation cursors advance exactly once per checkpoint for every
+// particle alike, so they are the round number and are not stored per
+// particle.
+#pragma once
+
+#include "devmath.hpp"
+
+namespace pcfg {
+
+constexpr uint8_t kStop = 255;  // b_stop
+
+// Constant model data on the device (uploaded by smc_model_register).
+struct ModelDev {
+    int32_t kind, precision, checkpoint, n_nodes, T, stack_depth;
+    const int32_t* parent;
+    const int32_t* left;
+    const double* age;
+    const double* y;
+    const int32_t* sp_before;  // ClaDS: pending-stack size when node r is visited
+    double p[16];
+    // constants derived on the device with the pinned functions
+    double ln2, log_rho, corr, log_w, obs_c, obs_var;
+};
+
+// ---------------------------------------------------------------------------
+// Weighted geometric program (Sec. 2, Fig. 2). State: flips (int).
+// ---------------------------------------------------------------------------
+struct Geometric {
+    static constexpr int kReal = 0, kInt = 1;
+    struct State {
+        int flips;
+    };
+    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t /*round*/, uint8_t /*b*/, State& st,
+                                         double& lw, Stream& s, bool& ckpt)
+    {
+        const bool heads = draw_bernoulli(s, m.p[0]);
+        st.flips += 1;
+        if (heads) {
+            lw = lw + m.log_w;
+            ckpt = m.checkpoint != 0;
+            return 0;
+        }
+        ckpt = true;
+        return kStop;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Linear-Gaussian state-space model (eq. (2), Fig. 4). State: x.
+// Block 0 draws x_0 and jumps to block 1 without a checkpoint; block 1 moves x,
+// observes y_t, and checkpoints (b_stop after the last observation).
+// ---------------------------------------------------------------------------
+template <class Real>
+struct Lgssm {
+    static constexpr int kReal = 1, kInt = 0;
+    struct State {
+        double x;
+    };
+    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
+                                         Stream& s, bool& ckpt)
+    {
+        if (b == 0) {
+            const double z = draw_normal(s);
+            st.x = (double)(Real)(m.p[4] + m.p[5] * z);
+            ckpt = false;
+            return 1;
+        }
+        const double z = draw_normal(s);
+        st.x = (double)(Real)((m.p[0] * st.x + m.p[1]) + m.p[2] * z);
+        const double d = m.y[round] - st.x;
+        lw = lw + (m.obs_c - (d * d) / (2.0 * m.obs_var));
+        ckpt = true;
+        return (int)round + 1 == m.T ? kStop : 1;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Constant-rate birth-death (Appendix B listing). State: lambda, mu.
+// Block 0 draws the rates and adds the correction weight; block 1 handles the
+// observed branch above node `round` (preorder, left subtree first).
+// ---------------------------------------------------------------------------
+constexpr int kMaxDepthCap = 32;
+
+struct CrbdFrame {
+    int remaining;
+    double start, length;
+};
+
+struct CrbdSim {
+    double lambda, mu, rho;
+    int events, max_events, max_depth;
+
+    // A hidden lineage born at age t0 goes undetected (crbdGoesUndetected): its
+    // lifetime is Exponential(mu); if it outlives the present it is detected
+    // with probability rho; along its life it speciates Poisson(lambda * life)
+    // times, and each daughter (born at a uniform time) must go undetected too.
+    // Evaluated depth-first with an explicit frame stack; any detection, or
+    // exceeding the depth or event budget, answers "detected".
+    __device__ inline bool undetected(Stream& s, double t0)
+    {
+        CrbdFrame stack[kMaxDepthCap];
+        int depth = 0;
+        double enter_at = t0;
+        bool entering = true;
+        while (true) {
+            if (entering) {
+                if (depth + 1 > max_depth) return false;
+                const double life = draw_exponential(s, mu);
+                if (life > enter_at) {
+                    if (draw_bernoulli(s, rho)) return false;
+                }
+                const double len = life < enter_at ? life : enter_at;
+                const int n = draw_poisson(s, lambda * len);
+                if (n < 0) return false;
+                stack[depth] = CrbdFrame{n, enter_at, len};
+                depth += 1;
+                entering = false;
+            }
+            CrbdFrame& top = stack[depth - 1];
+            if (top.remaining == 0) {
+                depth -= 1;
+                if (depth == 0) return true;
+                continue;
+            }
+            top.remaining -= 1;
+            if (events >= max_events) return false;
+            events += 1;
+            const double a = top.start - top.length;
+            enter_at = draw_uniform(s, a, top.start);
+            entering = true;
+        }
+    }
+};
+
+template <class Real>
+struct Crbd {
+    static constexpr int kReal = 2, kInt = 0;
+    struct State {
+        double lambda, mu;
+    };
+    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
+                                         Stream& s, bool& ckpt)
+    {
+        ckpt = true;
+        if (b == 0) {
+            const double lambda = m.p[3] > 0.0 ? m.p[3] : draw_gamma1(s, m.p[1]);
+            const double mu = m.p[4] >= 0.0 ? m.p[4] : draw_gamma1(s, m.p[2]);
+            st.lambda = (double)(Real)lambda;
+            st.mu = (double)(Real)mu;
+            lw = lw + m.corr;
+            return m.n_nodes > 1 ? 1 : kStop;
+        }
+        const int node = (int)round;
+        const double tp = m.age[m.parent[node]];
+        const double tc = m.age[node];
+        const double ln1 = -st.mu * (tp - tc);
+        const double ln2 = m.left[node] >= 0 ? fn::log(st.lambda) : m.log_rho;
+        const int n = draw_poisson(s, st.lambda * (tp - tc));
+        double ln3 = 0.0;
+        if (n < 0) {
+            ln3 = -__builtin_huge_val();
+        } else {
+            CrbdSim sim{st.lambda, st.mu, m.p[0], 0, (int)m.p[5], (int)m.p[6]};
+            for (int e = 0; e < n; ++e) {
+                if (sim.events >= sim.max_events) {
+                    ln3 = -__builtin_huge_val();
+                    break;
+                }
+                sim.events += 1;
+                const double t = draw_uniform(s, tc, tp);
+                if (!sim.undetected(s, t)) {
+                    ln3 = -__builtin_huge_val();
+                    break;
+                }
+                ln3 = ln3 + m.ln2;
+            }
+        }
+        lw = lw + (ln1 + (ln2 + ln3));
+        return node + 1 < m.n_nodes ? 1 : kStop;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Birth-death with cladogenetic rate shifts (ClaDS-style). State: current
+// lineage rate lambda, eps, alpha, sigma, plus a stack of pending right-
+// daughter rates (its size is the same for every particle: sp_before[round]).
+// ---------------------------------------------------------------------------
+struct ClaDSSide {
+    double eps, log_alpha, sigma, rho;
+    int events, max_events, max_depth;
+
+    // A side lineage born at age t0 with rate r0 must die out unobserved: events
+    // arrive at rate r (1 + eps); an event is a speciation with probability
+    // 1/(1+eps) (both daughters get r * LogNormal(log alpha, sigma)) and an
+    // extinction otherwise; reaching the present is detection with prob. rho.
+    // Depth-first: the second daughter waits on a stack while the first one's
+    // subtree is simulated.
+    struct Pending {
+        double start, rate;
+        int depth;
+    };
+    __device__ inline bool undetected(Stream& s, double t0, double r0)
+    {
+        Pending stack[kMaxDepthCap];
+        int top = 0;
+        double start = t0, rate = r0;
+        int depth = 1;
+        while (true) {
+            bool lineage_done = false;
+            if (depth > max_depth) return false;
+            if (events >= max_events) return false;
+            events += 1;
+            const double w = draw_exponential(s, rate * (1.0 + eps));
+            if (start - w <= 0.0) {
+                if (draw_bernoulli(s, rho)) return false;
+                lineage_done = true;
+            } else {
+                const double t = start - w;
+                if (s.uniform() < 1.0 / (1.0 + eps)) {
+                    const double d1 = rate * draw_lognormal(s, log_alpha, sigma);
+                    const double d2 = rate * draw_lognormal(s, log_alpha, sigma);
+                    stack[top] = Pending{t, d2, depth + 1};
+                    top += 1;
+                    start = t;
+                    rate = d1;
+                    depth = depth + 1;
+                } else {
+                    lineage_done = true;
+                }
+            }
+            if (lineage_done) {
+                if (top == 0) return true;
+                top -= 1;
+                start = stack[top].start;
+                rate = stack[top].rate;
+                depth = stack[top].depth;
+            }
+        }
+    }
+};
+
+template <class Real>
+struct Clads {
+    static constexpr int kReal = 4, kInt = 0;
+    struct State {
+        double lambda, eps, alpha, sigma;
+    };
+    // Stack access for the particle: level k of this particle's pending rates.
+    struct StackIO {
+        const Real* in;   // gathered source (previous buffer, particle src), may be null in round 0
+        Real* out;        // this particle's column in the output buffer
+        uint64_t stride;  // particles per level
+        uint32_t src, dst;
+    };
+    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
+                                         Stream& s, bool& ckpt, const StackIO& io)
+    {
+        ckpt = true;
+        if (b == 0) {
+            const double l0 = m.p[9] > 0.0 ? m.p[9] : draw_gamma1(s, m.p[1]);
+            const double eps = m.p[10] >= 0.0 ? m.p[10] : draw_uniform(s, m.p[2], m.p[3]);
+            const double alpha = m.p[11] > 0.0 ? m.p[11] : draw_uniform(s, m.p[4], m.p[5]);
+            const double sigma = m.p[12] >= 0.0 ? m.p[12] : draw_gamma1(s, m.p[6]);
+            st.eps = (double)(Real)eps;
+            st.alpha = (double)(Real)alpha;
+            st.sigma = (double)(Real)sigma;
+            lw = lw + m.corr;
+            const double log_alpha = fn::log(st.alpha);
+            const double left = l0 * draw_lognormal(s, log_alpha, st.sigma);
+            const double right = l0 * draw_lognormal(s, log_alpha, st.sigma);
+            io.out[io.dst] = (Real)right;  // level 0
+            st.lambda = (double)(Real)left;
+            return m.n_nodes > 1 ? 1 : kStop;
+        }
+        const int node = (int)round;
+        const int sp = m.sp_before[node];
+        const double log_alpha = fn::log(st.alpha);
+        ClaDSSide side{st.eps, log_alpha, st.sigma, m.p[0], 0, (int)m.p[7], (int)m.p[8]};
+        double lambda = st.lambda;
+        double t = m.age[m.parent[node]];
+        const double tc = m.age[node];
+        double w_acc = lw;
+        bool dead = false;
+        while (true) {
+            if (side.events >= side.max_events) {
+                dead = true;
+                break;
+            }
+            side.events += 1;
+            const double w = draw_exponential(s, lambda);
+            if (t - w <= tc) {
+                w_acc = w_acc + (-(st.eps * lambda) * (t - tc));
+                break;
+            }
+            w_acc = w_acc + (-(st.eps * lambda) * w);
+            t = t - w;
+            const double cont = lambda * draw_lognormal(s, log_alpha, st.sigma);
+            const double sider = lambda * draw_lognormal(s, log_alpha, st.sigma);
+            if (!side.undetected(s, t, sider)) {
+                dead = true;
+                break;
+            }
+            w_acc = w_acc + m.ln2;
+            lambda = cont;
+        }
+        const bool internal = m.left[node] >= 0;
+        // carry the live part of the stack (levels below sp) to this slot
+        for (int k = 0; k < sp; ++k) io.out[(uint64_t)k * io.stride + io.dst] = io.in[(uint64_t)k * io.stride + io.src];
+        if (dead) {
+            w_acc = -__builtin_huge_val();
+            if (internal) {
+                io.out[(uint64_t)sp * io.stride + io.dst] = (Real)lambda;
+                st.lambda = (double)(Real)lambda;
+            } else if (sp > 0) {
+                st.lambda = (double)io.in[(uint64_t)(sp - 1) * io.stride + io.src];
+            }
+        } else if (internal) {
+            w_acc = w_acc + fn::log(lambda);
+            const double left = lambda * draw_lognormal(s, log_alpha, st.sigma);
+            const double right = lambda * draw_lognormal(s, log_alpha, st.sigma);
+            io.out[(uint64_t)sp * io.stride + io.dst] = (Real)right;
+            st.lambda = (double)(Real)left;
+        } else {
+            w_acc = w_acc + m.log_rho;
+            if (sp > 0) st.lambda = (double)io.in[(uint64_t)(sp - 1) * io.stride + io.src];
+        }
+        lw = w_acc;
+        return node + 1 < m.n_nodes ? 1 : kStop;
+    }
+};
+
+}  // namespace pcfg
