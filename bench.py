@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of SMC over a PCFG on one MI355X: CRBD on a 256-tip tree, 2^20 particles.
+
+One step is one complete SMC run (Algorithm 1: initialisation, 511 rounds of
+propagation + resampling, final log Z) on the constant-rate birth-death model
+of the paper's appendix, conditioned on a synthetic 256-tip Yule tree, with
+FP32 particle state and FP64 log-weights and scan. The tree lives in device
+memory before timing starts and every run's buffers are allocated beforehand.
+Printed: one JSON line with canonical particle-block-steps/s (block executions
+excluding b_stop, per second of wall time of the timed runs), the dominant
+kernel's achieved bandwidth against MI355X's HBM peak, and the CPU oracle's
+throughput on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-block-steps/s at 2^20 CRBD particles; batched p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0
+TIPS, TREE_SEED, N_PARTICLES = 256, 3000, 1 << 20
+
+# Algorithmic bytes per particle per launch (FP32 state: lambda, mu).
+#  propagate: anc 4 + gathered blk 1 + gathered state 8 read; blk 1 + state 8 + lw 8 written
+#             (round 0 only writes: 17)
+#  reduce:    lw 8 read
+#  scan_anc:  lw 8 read, anc 4 written (not launched usefully in the final round)
+def bytes_per_launch(kernel: str, n: int, rounds: int) -> float:
+    if kernel == "propagate":
+        return n * (17 + 30 * (rounds - 1)) / rounds
+    if kernel == "reduce":
+        return n * 8.0
+    return n * 12.0 * (rounds - 1) / rounds
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2112_00364_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, n_launch_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_crbd_yule256_n2p20.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("source_sha") != kernel_source_hash() or kernel not in d.get("kernels", {}):
+        return None
+    k = d["kernels"][kernel]
+    return k["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(spec, n: int):
+    from oracle import oracle as O
+    O.build()
+    t0 = time.perf_counter()
+    r = O.Run(spec, n, 7)
+    st = r.run_to_end()
+    dt = time.perf_counter() - t0
+    assert st == O.FINISHED
+    return {"value": r.block_steps / dt, "unit": "particle-block-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"CRBD, {TIPS}-tip Yule tree (seed {TREE_SEED}), {n} particles, all {r.round + 1} rounds, "
+                      f"single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed SMC runs")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed SMC runs first")
+    ap.add_argument("--cpu-particles", type=int, default=1 << 16,
+                    help="particles in the CPU oracle's bounded sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the SMC path here runs on a single MI355X; "
+              "independent runs shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2112_00364_amd import inputs as I
+    from paper_2112_00364_amd import smc
+
+    tree = I.yule_tree(TIPS, TREE_SEED)
+    spec = I.crbd_spec(tree, precision=32)
+    rounds = 2 * TIPS - 1
+    ctx = smc.Context(0)
+    model = smc.Model(ctx, spec)
+    stream = ctx.stream
+    runs = [smc.Run(model, N_PARTICLES, 1 + i) for i in range(args.warmup + args.steps)]
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        runs[i].run_to_end()
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for r in runs[args.warmup:]:
+        r.run_to_end()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = start.elapsed_time(end)
+    steps_total = 0
+    log_zs = []
+    for r in runs[args.warmup:]:
+        s = r.stats()
+        assert s["status"] == smc.FINISHED and s["block_steps"] == N_PARTICLES * rounds, s
+        steps_total += s["block_steps"]
+        log_zs.append(s["log_z"])
+    for r in runs:
+        r.close()
+    ms_per_step = gpu_ms / args.steps
+    value = steps_total / (gpu_ms / 1e3)
+
+    roofline = None
+    kernels = None
+    if not args.no_profile:
+        prof = smc.Run(model, N_PARTICLES, 12345)
+        prof.profile(True)
+        prof.run_to_end()
+        times = prof.kernel_times()
+        prof.close()
+        kernels = {}
+        for k, (ms, launches) in times.items():
+            avg_ms = ms / launches
+            b = bytes_per_launch(k, N_PARTICLES, rounds)
+            kernels[k] = {"avg_us": avg_ms * 1e3, "launches": launches, "alg_bytes_per_launch": b,
+                          "achieved_GBs": b / (avg_ms * 1e-3) / 1e9}
+        dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+        kd = kernels[dom]
+        traffic = measured_traffic(dom, kd["alg_bytes_per_launch"])
+        roofline = {"bound": "hbm", "achieved": round(kd["achieved_GBs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dom,
+                    "avg_launch_us": round(kd["avg_us"], 3)}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-block-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"crbd_yule{TIPS}_n2^20", "tips": TIPS, "tree_seed": TREE_SEED,
+                   "particles": N_PARTICLES, "rounds_per_run": rounds, "state": "f32",
+                   "log_weights": "f64", "step": "one complete SMC run"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "wall_s_timed": wall,
+        "log_z": log_zs,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_particles)
+    print(json.dumps(out))
+    model.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

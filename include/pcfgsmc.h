@@ -174,6 +174,18 @@ smc_status smc_run_stats(smc_run* run, smc_stats* out);
 
 smc_status smc_run_destroy(smc_run* run); /* NULL-safe */
 
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * every launch a run makes while profiling is on (smc_step, smc_resample,
+ * smc_run_to_end). Index 0 = propagation, 1 = reduction (log Z), 2 = scan and
+ * ancestors; ms = summed durations, launches = count. smc_profile(run, 1)
+ * clears previous records; both calls synchronise. */
+typedef struct {
+    double ms[3];
+    uint64_t launches[3];
+} smc_kernel_times;
+smc_status smc_profile(smc_run* run, int32_t enable);
+smc_status smc_profile_read(smc_run* run, smc_kernel_times* out);
+
 /* Resampling alone (Algorithm 1 step 3) on a device array of n log-weights:
  * writes the log Z increment (device double) and the n ancestors (device
  * uint32) for round `round` under `seed`. lw, anc and logz_inc are device

@@ -115,6 +115,28 @@ struct smc_run {
     uint32_t rounds_issued = 0;
     int32_t known_status = SMC_OK;
     DeviceArena arena;
+    // optional per-kernel timing: (kernel id, start event, end event)
+    bool profiling = false;
+    struct Timed {
+        int kernel;
+        hipEvent_t start, end;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
+    size_t events_used = 0;
+    hipEvent_t next_event()
+    {
+        if (events_used == event_pool.size()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            event_pool.push_back(e);
+        }
+        return event_pool[events_used++];
+    }
+    ~smc_run()
+    {
+        for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -192,7 +214,14 @@ smc_status do_step(smc_run* r)
 {
     if (!r->expect_step) return fail(SMC_ERR_STATE, "smc_step called twice without smc_resample");
     if (r->known_status != SMC_OK) return r->known_status;
-    HIP_TRY(launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, r->ctx->stream));
+    hipStream_t st = r->ctx->stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (r->profiling && (a = r->next_event()) && (b = r->next_event())) HIP_TRY(hipEventRecord(a, st));
+    HIP_TRY(launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, st));
+    if (a && b) {
+        HIP_TRY(hipEventRecord(b, st));
+        r->timed.push_back(smc_run::Timed{0, a, b});
+    }
     r->expect_step = false;
     return SMC_OK;
 }
@@ -201,7 +230,20 @@ smc_status do_resample(smc_run* r)
 {
     if (r->expect_step) return fail(SMC_ERR_STATE, "smc_resample called before smc_step");
     if (r->known_status != SMC_OK) return r->known_status;
-    HIP_TRY(launch_resample(r->dev, r->red_tiles, r->n_red, r->ctx->stream));
+    hipStream_t st = r->ctx->stream;
+    if (r->profiling) {
+        hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
+        if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
+        HIP_TRY(hipEventRecord(a, st));
+        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, st));
+        HIP_TRY(hipEventRecord(b, st));
+        HIP_TRY(launch_scan_anc(r->dev, r->red_tiles, r->n_red, st));
+        HIP_TRY(hipEventRecord(c, st));
+        r->timed.push_back(smc_run::Timed{1, a, b});
+        r->timed.push_back(smc_run::Timed{2, b, c});
+    } else {
+        HIP_TRY(launch_resample(r->dev, r->red_tiles, r->n_red, st));
+    }
     r->expect_step = true;
     r->rounds_issued += 1;
     return SMC_OK;
@@ -516,6 +558,30 @@ smc_status smc_run_stats(smc_run* r, smc_stats* out)
     out->block_steps = c.block_steps;
     out->log_z = c.log_z;
     out->stack_depth = r->model->stack_depth;
+    return SMC_OK;
+}
+
+smc_status smc_profile(smc_run* r, int32_t enable)
+{
+    if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    HIP_TRY(hipStreamSynchronize(r->ctx->stream));
+    r->profiling = enable != 0;
+    r->timed.clear();
+    r->events_used = 0;
+    return SMC_OK;
+}
+
+smc_status smc_profile_read(smc_run* r, smc_kernel_times* out)
+{
+    if (!r || !out) return fail(SMC_ERR_INVALID, "NULL argument");
+    HIP_TRY(hipStreamSynchronize(r->ctx->stream));
+    std::memset(out, 0, sizeof(*out));
+    for (const auto& t : r->timed) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, t.start, t.end));
+        out->ms[t.kernel] += ms;
+        out->launches[t.kernel] += 1;
+    }
     return SMC_OK;
 }
 

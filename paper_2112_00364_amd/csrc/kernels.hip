@@ -537,12 +537,25 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     return hipGetLastError();
 }
 
-hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
+hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce, dim3(n_tiles), dim3(kRedThreads), 0, st, runs, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
+{
+    if (n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scan_anc, dim3(n_tiles), dim3(kRedThreads), 0, st, runs, tiles);
     return hipGetLastError();
+}
+
+hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
+{
+    hipError_t e = launch_reduce(runs, tiles, n_tiles, st);
+    if (e != hipSuccess) return e;
+    return launch_scan_anc(runs, tiles, n_tiles, st);
 }
 
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)

@@ -10,6 +10,8 @@ namespace pcfg {
 hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const TileRef* tiles, uint32_t n_tiles,
                             hipStream_t st);
 hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
+hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
+hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
 hipError_t launch_gather(int elem_bytes, const void* src, const uint32_t* anc, void* dst, uint64_t n,
                          uint64_t levels, uint64_t stride, hipStream_t st);

@@ -53,6 +53,10 @@ class _Stats(C.Structure):
                 ("log_z", C.c_double), ("stack_depth", C.c_int32)]
 
 
+class _KernelTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 3), ("launches", C.c_uint64 * 3)]
+
+
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
 _FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
@@ -86,6 +90,8 @@ def lib():
         "smc_read": [vp, i32, vp, C.c_size_t],
         "smc_run_stats": [vp, C.POINTER(_Stats)],
         "smc_run_destroy": [vp],
+        "smc_profile": [vp, i32],
+        "smc_profile_read": [vp, C.POINTER(_KernelTimes)],
         "smc_resample_weights": [vp, vp, u64, u64, u32, vp, vp],
         "smc_batch_create": [vp, C.POINTER(vp)],
         "smc_batch_add": [vp, vp, u64, u64, C.POINTER(i32)],
@@ -258,6 +264,16 @@ class Run:
         _check(lib().smc_run_stats(self._h, C.byref(s)))
         return {"round": s.round, "status": s.status, "block_steps": s.block_steps, "log_z": s.log_z,
                 "stack_depth": s.stack_depth}
+
+    def profile(self, enable: bool = True):
+        _check(lib().smc_profile(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """{kernel: (total ms, launches)} for propagate, reduce, scan_anc."""
+        t = _KernelTimes()
+        _check(lib().smc_profile_read(self._h, C.byref(t)))
+        names = ("propagate", "reduce", "scan_anc")
+        return {names[i]: (t.ms[i], int(t.launches[i])) for i in range(3)}
 
     def _read(self, what, dtype, count=1):
         out = np.zeros(self.n * count, dtype=dtype)
