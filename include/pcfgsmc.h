@@ -149,8 +149,15 @@ smc_status smc_done(smc_run* run, int32_t* done);
 /* Normalising-constant estimate so far (synchronises). */
 smc_status smc_log_z(smc_run* run, double* out);
 
-/* Step and resample until the run ends (checks termination every few rounds). */
+/* Step and resample until the run ends. For models whose particles advance in
+ * lockstep (LGSSM, CRBD, CLADS) a run starting at round 0 replays one captured
+ * HIP graph of all its rounds (captured on the first call); otherwise it checks
+ * termination every 16 rounds. Returns SMC_FINISHED or the failure status. */
 smc_status smc_run_to_end(smc_run* run);
+
+/* Algorithm 1 step 1 again on the run's existing buffers, with a new seed:
+ * no allocation; the next smc_run_to_end replays the captured graph. */
+smc_status smc_reset(smc_run* run, uint64_t seed);
 
 /* Copy per-particle data to a caller-owned host buffer (synchronises).
  * what: SMC_READ_BLK (uint8 per particle; 255 = b_stop), SMC_READ_LW (double),

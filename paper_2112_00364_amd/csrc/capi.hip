@@ -124,6 +124,9 @@ struct smc_run {
     std::vector<Timed> timed;
     std::vector<hipEvent_t> event_pool;
     size_t events_used = 0;
+    // the whole lockstep run (rounds 0..R-1) captured once and replayed
+    hipGraphExec_t graph = nullptr;
+    uint32_t graph_rounds = 0;
     hipEvent_t next_event()
     {
         if (events_used == event_pool.size()) {
@@ -136,6 +139,7 @@ struct smc_run {
     ~smc_run()
     {
         for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+        if (graph) (void)hipGraphExecDestroy(graph);
     }
 };
 
@@ -176,6 +180,7 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     }
     h.lw = (double*)get(n * 8);
     h.anc = (uint32_t*)get(n * 4);
+    if (m->kind == SMC_MODEL_CRBD || m->kind == SMC_MODEL_CLADS) h.deep_list = (uint32_t*)get(n * 4);
     h.part_q = (double*)get(h.red_tiles * 8);
     h.part_e = (double*)get(h.red_tiles * 8);
     h.prefix = (double*)get(h.red_tiles * 8);
@@ -184,7 +189,7 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     r->n_red = h.red_tiles;
     r->prop_tiles = (TileRef*)get(sizeof(TileRef) * r->n_prop);
     r->red_tiles = (TileRef*)get(sizeof(TileRef) * r->n_red);
-    bool ok = h.ctl && h.lw && h.anc && h.part_q && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
+    bool ok = h.ctl && h.lw && h.anc && h.part_q && (h.deep_list || m->kind < SMC_MODEL_CRBD) && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
     for (int b = 0; b < 2; ++b) {
         ok = ok && h.buf[b].blk;
         for (int f = 0; f < real_fields(m->kind); ++f) ok = ok && h.buf[b].real[f];
@@ -218,6 +223,7 @@ smc_status do_step(smc_run* r)
     hipEvent_t a = nullptr, b = nullptr;
     if (r->profiling && (a = r->next_event()) && (b = r->next_event())) HIP_TRY(hipEventRecord(a, st));
     HIP_TRY(launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, st));
+    HIP_TRY(launch_propagate_deep(r->model->kind, r->model->precision, r->dev, 1, st));
     if (a && b) {
         HIP_TRY(hipEventRecord(b, st));
         r->timed.push_back(smc_run::Timed{0, a, b});
@@ -440,14 +446,54 @@ smc_status smc_log_z(smc_run* r, double* out)
     return c.status;
 }
 
+// Capture rounds 0..R-1 of a lockstep model (propagation, reduction, scan per
+// round) as one graph. Capture needs a non-legacy stream, so it records on a
+// private stream; the graph is then launched on the context's stream.
+static smc_status capture_run(smc_run* r, uint32_t rounds)
+{
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    for (uint32_t k = 0; k < rounds && e == hipSuccess; ++k) {
+        e = launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, cap);
+        if (e == hipSuccess) e = launch_propagate_deep(r->model->kind, r->model->precision, r->dev, 1, cap);
+        if (e == hipSuccess) e = launch_resample(r->dev, r->red_tiles, r->n_red, cap);
+    }
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&r->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        r->graph = nullptr;
+        return fail(SMC_ERR_DEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+    }
+    r->graph_rounds = rounds;
+    return SMC_OK;
+}
+
 smc_status smc_run_to_end(smc_run* r)
 {
     if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    if (r->known_status != SMC_OK) return r->known_status;
+    const uint32_t known = lockstep_rounds(r->model);
+    if (known && r->rounds_issued == 0 && r->expect_step && !r->profiling) {
+        if (!r->graph) {
+            smc_status s = capture_run(r, known);
+            if (s != SMC_OK) return s;
+        }
+        HIP_TRY(hipGraphLaunch(r->graph, r->ctx->stream));
+        r->rounds_issued = known;
+        RunCtl c;
+        smc_status s = read_ctl(r, &c);
+        if (s != SMC_OK) return s;
+        if (c.status != SMC_OK) return c.status;
+    }
     if (!r->expect_step) {
         smc_status s = do_resample(r);
         if (s != SMC_OK) return s;
     }
-    const uint32_t known = lockstep_rounds(r->model);
     uint32_t chunk = 16;
     if (known && r->rounds_issued < known) chunk = known - r->rounds_issued;
     for (;;) {
@@ -463,6 +509,18 @@ smc_status smc_run_to_end(smc_run* r)
         if (c.status != SMC_OK) return c.status;
         chunk = 16;
     }
+}
+
+smc_status smc_reset(smc_run* r, uint64_t seed)
+{
+    if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    HIP_TRY(launch_reset(r->dev, seed, r->ctx->stream));
+    r->host.seed = seed;
+    r->seed = seed;
+    r->expect_step = true;
+    r->rounds_issued = 0;
+    r->known_status = SMC_OK;
+    return SMC_OK;
 }
 
 smc_status smc_read(smc_run* r, int32_t what, void* dst, size_t bytes)
@@ -757,6 +815,8 @@ smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
     hipStream_t st = b->ctx->stream;
     for (int32_t k = 0; k < rounds; ++k) {
         for (const auto& g : b->groups) HIP_TRY(launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, st));
+        for (const auto& g : b->groups)
+            HIP_TRY(launch_propagate_deep(g.kind, g.precision, b->runs, (uint32_t)b->runs_h.size(), st));
         HIP_TRY(launch_resample(b->runs, b->red_tiles, b->n_red, st));
     }
     for (smc_run* r : b->slots)

@@ -45,7 +45,9 @@ __host__ __device__ inline Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
 enum : uint32_t { kTagPropagate = 0, kTagResample = 1 };
 
 // One particle's words for one round, drawn in program order. Word k is lane
-// k%4 of the Philox block with counter {k/4, particle, round, tag}.
+// k%4 of the Philox block with counter {k/4, particle, round, tag}. The block
+// is consumed as a shift register (always lane 0 next), so every register
+// index is static and the buffer never lands in scratch memory.
 struct Stream {
     uint32_t key0, key1, particle, round, tag;
     uint32_t k;
@@ -63,13 +65,12 @@ struct Stream {
 
     __device__ inline uint32_t next()
     {
-        const uint32_t lane = k & 3u;
-        if (lane == 0u) buf = philox10(k >> 2, particle, round, tag, key0, key1);
+        if ((k & 3u) == 0u) buf = philox10(k >> 2, particle, round, tag, key0, key1);
         k += 1u;
-        uint32_t w = buf.w3;
-        w = (lane == 0u) ? buf.w0 : w;
-        w = (lane == 1u) ? buf.w1 : w;
-        w = (lane == 2u) ? buf.w2 : w;
+        const uint32_t w = buf.w0;
+        buf.w0 = buf.w1;
+        buf.w1 = buf.w2;
+        buf.w2 = buf.w3;
         return w;
     }
 

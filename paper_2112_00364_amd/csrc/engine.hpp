@@ -19,7 +19,8 @@ struct alignas(64) RunCtl {
     uint32_t active;                 // particles not at b_stop after this round's propagation
     uint32_t bad;                    // a NaN or +inf log-weight was produced
     uint32_t ticket;                 // work-groups done in the reduction
-    uint32_t pad[4];
+    uint32_t deep_count;             // particles handed to the deep-stack pass this round
+    uint32_t pad[3];
 };
 
 // One particle buffer: block index, real fields (storage precision), int
@@ -40,6 +41,7 @@ struct RunDev {
     ParticleBuf buf[2];  // buf[r & 1] is written by the propagation of round r
     double* lw;
     uint32_t* anc;
+    uint32_t* deep_list; // particles whose hidden-lineage stack outgrew the registers
     double* part_q;      // per reduction tile: sum of grid units
     double* part_e;      // per reduction tile: sum of exp(lw - M)
     double* prefix;      // per reduction tile: grid units before the tile

@@ -17,6 +17,8 @@
 //                (systematic resampling, Sec. 3.3).
 // Memory is structure-of-arrays (Sec. 3.3): consecutive lanes touch
 // consecutive elements of each field.
+#include <type_traits>
+
 #include "engine.hpp"
 #include "launch.hpp"
 
@@ -123,6 +125,89 @@ __device__ inline void store_real(void* p, uint32_t i, double v)
     static_cast<Real*>(p)[i] = (Real)v;
 }
 
+// One particle slot j of round `round`: gather (block, state) from the
+// ancestor src, run blocks until a checkpoint or b_stop, store the results.
+// Returns false (storing nothing) when the hidden-lineage stack overflowed.
+template <int Kind, class Real, bool kFast>
+__device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t j, uint32_t round, uint8_t& blk,
+                                    double& lw, uint32_t& steps)
+{
+    const ParticleBuf& out = R.buf[round & 1u];
+    const ParticleBuf& in = R.buf[(round & 1u) ^ 1u];
+    const uint32_t src = round > 0 ? R.anc[j] : j;
+    blk = round > 0 ? in.blk[src] : 0;
+    lw = 0.0;
+    steps = 0;
+    Stream s;
+    s.start(R.seed, j, round, kTagPropagate);
+    bool overflow = false;
+    if constexpr (Kind == 0) {
+        Geometric::State st{round > 0 ? in.ints[0][src] : 0};
+        while (blk != kStop) {
+            bool ck = false;
+            blk = Geometric::sim(m, round, blk, st, lw, s, ck);
+            steps += 1;
+            if (ck) break;
+        }
+        out.ints[0][j] = st.flips;
+    } else if constexpr (Kind == 1) {
+        typename Lgssm<Real>::State st{round > 0 ? load_real<Real>(in.real[0], src) : 0.0};
+        while (blk != kStop) {
+            bool ck = false;
+            blk = Lgssm<Real>::sim(m, round, blk, st, lw, s, ck);
+            steps += 1;
+            if (ck) break;
+        }
+        store_real<Real>(out.real[0], j, st.x);
+    } else if constexpr (Kind == 2) {
+        using Stack = typename std::conditional<kFast, RegFrames<CrbdFrame, kRegFrames>, ArrayFrames<CrbdFrame>>::type;
+        typename Crbd<Real>::State st{0.0, 0.0};
+        if (round > 0) {
+            st.lambda = load_real<Real>(in.real[0], src);
+            st.mu = load_real<Real>(in.real[1], src);
+        }
+        while (blk != kStop) {
+            bool ck = false;
+            blk = Crbd<Real>::template sim<Stack>(m, round, blk, st, lw, s, ck, overflow);
+            if (overflow) return false;
+            steps += 1;
+            if (ck) break;
+        }
+        store_real<Real>(out.real[0], j, st.lambda);
+        store_real<Real>(out.real[1], j, st.mu);
+    } else {
+        using Stack =
+            typename std::conditional<kFast, RegFrames<ClaDSPending, kRegFrames>, ArrayFrames<ClaDSPending>>::type;
+        typename Clads<Real>::State st{0.0, 0.0, 0.0, 0.0};
+        if (round > 0) {
+            st.lambda = load_real<Real>(in.real[0], src);
+            st.eps = load_real<Real>(in.real[1], src);
+            st.alpha = load_real<Real>(in.real[2], src);
+            st.sigma = load_real<Real>(in.real[3], src);
+        }
+        typename Clads<Real>::StackIO io{static_cast<const Real*>(in.stack), static_cast<Real*>(out.stack),
+                                         (uint64_t)R.n, src, j};
+        while (blk != kStop) {
+            bool ck = false;
+            blk = Clads<Real>::template sim<Stack>(m, round, blk, st, lw, s, ck, io, overflow);
+            if (overflow) return false;
+            steps += 1;
+            if (ck) break;
+        }
+        store_real<Real>(out.real[0], j, st.lambda);
+        store_real<Real>(out.real[1], j, st.eps);
+        store_real<Real>(out.real[2], j, st.alpha);
+        store_real<Real>(out.real[3], j, st.sigma);
+    }
+    out.blk[j] = blk;
+    R.lw[j] = lw;
+    return true;
+}
+
+// Fast pass over every particle: hidden-lineage stacks live in registers. A
+// particle whose stack would need more frames is appended to the run's
+// overflow list instead and recomputed by k_propagate_deep (its random stream
+// is counter-based, so the recomputation draws the same words).
 template <int Kind, class Real>
 __global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __restrict__ runs,
                                                              const TileRef* __restrict__ tiles)
@@ -134,82 +219,28 @@ __global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __rest
     const uint32_t round = ctl->round;
     const ModelDev& m = *R.model;
     const uint32_t j = tr.tile * kPropThreads + threadIdx.x;
-    const bool valid = j < R.n;
-    const ParticleBuf& out = R.buf[round & 1u];
-    const ParticleBuf& in = R.buf[(round & 1u) ^ 1u];
-    const uint32_t src = (valid && round > 0) ? R.anc[j] : j;
-
-    uint8_t blk = 0;
+    bool counted = false;
+    uint8_t blk = kStop;
     double lw = 0.0;
     uint32_t steps = 0;
-    if (valid) {
-        if (round > 0) blk = in.blk[src];
-        Stream s;
-        s.start(R.seed, j, round, kTagPropagate);
-        if constexpr (Kind == 0) {
-            Geometric::State st{round > 0 ? in.ints[0][src] : 0};
-            while (blk != kStop) {
-                bool ck = false;
-                blk = Geometric::sim(m, round, blk, st, lw, s, ck);
-                steps += 1;
-                if (ck) break;
-            }
-            out.ints[0][j] = st.flips;
-        } else if constexpr (Kind == 1) {
-            typename Lgssm<Real>::State st{round > 0 ? load_real<Real>(in.real[0], src) : 0.0};
-            while (blk != kStop) {
-                bool ck = false;
-                blk = Lgssm<Real>::sim(m, round, blk, st, lw, s, ck);
-                steps += 1;
-                if (ck) break;
-            }
-            store_real<Real>(out.real[0], j, st.x);
-        } else if constexpr (Kind == 2) {
-            typename Crbd<Real>::State st{0.0, 0.0};
-            if (round > 0) {
-                st.lambda = load_real<Real>(in.real[0], src);
-                st.mu = load_real<Real>(in.real[1], src);
-            }
-            while (blk != kStop) {
-                bool ck = false;
-                blk = Crbd<Real>::sim(m, round, blk, st, lw, s, ck);
-                steps += 1;
-                if (ck) break;
-            }
-            store_real<Real>(out.real[0], j, st.lambda);
-            store_real<Real>(out.real[1], j, st.mu);
+    if (j < R.n) {
+        if (run_particle<Kind, Real, true>(R, m, j, round, blk, lw, steps)) {
+            counted = true;
         } else {
-            typename Clads<Real>::State st{0.0, 0.0, 0.0, 0.0};
-            if (round > 0) {
-                st.lambda = load_real<Real>(in.real[0], src);
-                st.eps = load_real<Real>(in.real[1], src);
-                st.alpha = load_real<Real>(in.real[2], src);
-                st.sigma = load_real<Real>(in.real[3], src);
-            }
-            typename Clads<Real>::StackIO io{static_cast<const Real*>(in.stack), static_cast<Real*>(out.stack),
-                                             (uint64_t)R.n, src, j};
-            while (blk != kStop) {
-                bool ck = false;
-                blk = Clads<Real>::sim(m, round, blk, st, lw, s, ck, io);
-                steps += 1;
-                if (ck) break;
-            }
-            store_real<Real>(out.real[0], j, st.lambda);
-            store_real<Real>(out.real[1], j, st.eps);
-            store_real<Real>(out.real[2], j, st.alpha);
-            store_real<Real>(out.real[3], j, st.sigma);
+            const uint32_t slot = atomicAdd(&ctl->deep_count, 1u);
+            R.deep_list[slot] = j;
         }
-        out.blk[j] = blk;
-        R.lw[j] = lw;
     }
 
     // work-group reduction: max key, bad flag, active count, block steps
     unsigned long long key = 0;
     uint32_t bad = 0, act = 0;
-    if (valid) {
+    if (counted) {
         if (lw != lw || lw == __builtin_huge_val()) bad = 1;
         else key = order_key(lw);
         act = blk != kStop ? 1u : 0u;
+    } else {
+        steps = 0;
     }
     key = wave_max_u64(key);
     bad = wave_sum(bad);
@@ -238,6 +269,33 @@ __global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __rest
         if (b) atomicOr(&ctl->bad, 1u);
         if (a) atomicAdd(&ctl->active, a);
         if (st) atomicAdd(&ctl->block_steps, (unsigned long long)st);
+    }
+}
+
+// Particles handed over by the fast pass, recomputed with a stack of
+// kMaxDepthCap frames. kDeepGroups work-groups per run stride over the run's
+// overflow list (usually a few dozen entries, often none).
+constexpr int kDeepGroups = 4;
+
+template <int Kind, class Real>
+__global__ __launch_bounds__(kPropThreads) void k_propagate_deep(const RunDev* __restrict__ runs)
+{
+    const RunDev& R = runs[blockIdx.x / kDeepGroups];
+    RunCtl* ctl = R.ctl;
+    if (ctl->status != 0 || R.model->kind != Kind || R.model->precision != (int)(8 * sizeof(Real))) return;
+    const uint32_t count = ctl->deep_count;
+    const uint32_t round = ctl->round;
+    const uint32_t first = (blockIdx.x % kDeepGroups) * kPropThreads + threadIdx.x;
+    for (uint32_t i = first; i < count; i += kDeepGroups * kPropThreads) {
+        const uint32_t j = R.deep_list[i];
+        uint8_t blk;
+        double lw;
+        uint32_t steps;
+        run_particle<Kind, Real, false>(R, *R.model, j, round, blk, lw, steps);
+        if (lw != lw || lw == __builtin_huge_val()) atomicOr(&ctl->bad, 1u);
+        else atomicMax(&ctl->maxkey, order_key(lw));
+        if (blk != kStop) atomicAdd(&ctl->active, 1u);
+        atomicAdd(&ctl->block_steps, (unsigned long long)steps);
     }
 }
 
@@ -295,38 +353,57 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
     if (!s_last) return;
     __threadfence();
 
-    // Last work-group of this run: fold the tile partials in tile order.
+    // Last work-group of this run: fold the tile partials (fixed order) and
+    // write each tile's exclusive offset in grid units (exact in FP64).
     const uint32_t T = R.red_tiles;
     const uint32_t per = (T + kRedThreads - 1) / kRedThreads;
     const uint32_t t0 = threadIdx.x * per;
+    const uint32_t t1 = t0 + per < T ? t0 + per : T;
+    // loads issued in batches of kBatch independent requests (one latency each)
+    constexpr int kBatch = 8;
     double q_local = 0.0, e_local = 0.0;
-    for (uint32_t t = t0; t < t0 + per && t < T; ++t) {
-        q_local += coherent_load(&R.part_q[t]);
-        e_local += coherent_load(&R.part_e[t]);
-    }
-    // exclusive scan of q_local over threads (exact: integer-valued doubles)
-    __shared__ double s_scan[kRedThreads];
-    __shared__ double s_esum[kRedThreads];
-    s_scan[threadIdx.x] = q_local;
-    s_esum[threadIdx.x] = e_local;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double run = 0.0, esum = 0.0;
-        for (int t = 0; t < kRedThreads; ++t) {
-            const double v = s_scan[t];
-            s_scan[t] = run;
-            run += v;
-            esum += s_esum[t];
+    for (uint32_t base = t0; base < t1; base += kBatch) {
+        double qb[kBatch], eb[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const bool in = base + k < t1;
+            qb[k] = in ? coherent_load(&R.part_q[base + k]) : 0.0;
+            eb[k] = in ? coherent_load(&R.part_e[base + k]) : 0.0;
         }
-        s_q[0] = run;
-        s_e[0] = esum;
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            q_local += qb[k];
+            e_local += eb[k];
+        }
     }
+    double q_incl = q_local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double o = __shfl_up(q_incl, off, 64);
+        if (lane >= off) q_incl += o;
+    }
+    const double e_wave = wave_sum(e_local);
+    __shared__ double s_qw[kRedThreads / 64];
+    if (lane == 63) s_qw[wave] = q_incl;
+    if (lane == 0) s_e[wave] = e_wave;
     __syncthreads();
+    double q_before = 0.0, q_all = 0.0, e_all = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) {
+        if (w < wave) q_before += s_qw[w];
+        q_all += s_qw[w];
+        e_all += s_e[w];
+    }
     {
-        double run = s_scan[threadIdx.x];
-        for (uint32_t t = t0; t < t0 + per && t < T; ++t) {
-            R.prefix[t] = run;
-            run += coherent_load(&R.part_q[t]);
+        double run = q_before + (q_incl - q_local);
+        for (uint32_t base = t0; base < t1; base += kBatch) {
+            double qb[kBatch];
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) qb[k] = base + k < t1 ? coherent_load(&R.part_q[base + k]) : 0.0;
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if (base + k < t1) R.prefix[base + k] = run;
+                run += qb[k];
+            }
         }
     }
     if (threadIdx.x == 0) {
@@ -337,13 +414,13 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
             ctl->log_z = -__builtin_huge_val();
             ctl->status = -6;  // SMC_DEGENERATE
         } else {
-            const double S = s_e[0];
+            const double S = e_all;
             ctl->log_z = ctl->log_z + ((M + fn::log(S)) - fn::log((double)R.n));
             if (ctl->active == 0) {
                 ctl->status = 1;  // SMC_FINISHED
             } else {
                 ctl->m_cur = M;
-                ctl->qtot = s_q[0];
+                ctl->qtot = q_all;
                 ctl->u = philox10(0u, 0u, round, kTagResample, (uint32_t)R.seed, (uint32_t)(R.seed >> 32)).w0;
                 ctl->round = round + 1;
             }
@@ -352,6 +429,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
         ctl->active = 0;
         ctl->bad = 0;
         ctl->ticket = 0;
+        ctl->deep_count = 0;
         __threadfence();
     }
 }
@@ -499,6 +577,27 @@ __global__ void k_selftest_philox(const uint32_t* __restrict__ ctr, const uint32
     out[4 * i + 3] = w.w3;
 }
 
+// Algorithm 1 step 1 again on existing buffers: round 0, zero log Z, new seed.
+// (A kernel rather than a memset so that it can sit inside a captured graph.)
+__global__ void k_reset(RunDev* run, uint64_t seed)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    run->seed = seed;
+    RunCtl* c = run->ctl;
+    c->maxkey = 0;
+    c->block_steps = 0;
+    c->log_z = 0.0;
+    c->m_cur = 0.0;
+    c->qtot = 0.0;
+    c->u = 0;
+    c->round = 0;
+    c->status = 0;
+    c->active = 0;
+    c->bad = 0;
+    c->ticket = 0;
+    c->deep_count = 0;
+}
+
 // Derived model constants, computed with the pinned device functions so that
 // every weight term has the same bits as on any other conforming evaluator.
 __global__ void k_model_setup(ModelDev* m)
@@ -534,6 +633,18 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     else if (kind == 2) hipLaunchKernelGGL((k_propagate<2, double>), g, b, 0, st, runs, tiles);
     else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate<3, float>), g, b, 0, st, runs, tiles);
     else hipLaunchKernelGGL((k_propagate<3, double>), g, b, 0, st, runs, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate_deep(int kind, int precision, const RunDev* runs, uint32_t n_runs, hipStream_t st)
+{
+    // only the birth-death models have hidden-lineage stacks
+    if (n_runs == 0 || kind < 2) return hipSuccess;
+    dim3 g(n_runs * kDeepGroups), b(kPropThreads);
+    if (kind == 2 && precision == 32) hipLaunchKernelGGL((k_propagate_deep<2, float>), g, b, 0, st, runs);
+    else if (kind == 2) hipLaunchKernelGGL((k_propagate_deep<2, double>), g, b, 0, st, runs);
+    else if (precision == 32) hipLaunchKernelGGL((k_propagate_deep<3, float>), g, b, 0, st, runs);
+    else hipLaunchKernelGGL((k_propagate_deep<3, double>), g, b, 0, st, runs);
     return hipGetLastError();
 }
 
@@ -586,6 +697,12 @@ hipError_t launch_selftest_math(int op, const double* in, double* out, uint64_t 
 hipError_t launch_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_selftest_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ctr, key, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(RunDev* run, uint64_t seed, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, run, seed);
     return hipGetLastError();
 }
 

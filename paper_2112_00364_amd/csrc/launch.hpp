@@ -9,6 +9,7 @@ namespace pcfg {
 
 hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const TileRef* tiles, uint32_t n_tiles,
                             hipStream_t st);
+hipError_t launch_propagate_deep(int kind, int precision, const RunDev* runs, uint32_t n_runs, hipStream_t st);
 hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
 hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
 hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
@@ -19,5 +20,6 @@ hipError_t launch_selftest_math(int op, const double* in, double* out, uint64_t 
 hipError_t launch_selftest_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, uint64_t n,
                                   hipStream_t st);
 hipError_t launch_model_setup(ModelDev* m, hipStream_t st);
+hipError_t launch_reset(RunDev* run, uint64_t seed, hipStream_t st);
 
 }  // namespace pcfg

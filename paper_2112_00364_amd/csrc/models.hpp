@@ -84,6 +84,45 @@ struct Lgssm {
 // observed branch above node `round` (preorder, left subtree first).
 // ---------------------------------------------------------------------------
 constexpr int kMaxDepthCap = 32;
+constexpr int kRegFrames = 4;  // frames held in registers on the fast path
+
+// Outcome of simulating one hidden lineage.
+enum Hidden : int { kDetected = 0, kUndetected = 1, kOverflow = 2 };
+
+// Depth-first frame stacks. RegFrames keeps the K innermost frames in
+// registers (every index is a compile-time constant, so no scratch memory is
+// needed) and reports full() when a K+1-th frame is asked for; ArrayFrames is
+// the unbounded-in-practice variant (kMaxDepthCap frames, placed in scratch).
+template <class Frame, int K>
+struct RegFrames {
+    Frame f[K];
+    int depth = 0;
+    __device__ inline bool full() const { return depth == K; }
+    __device__ inline Frame& top() { return f[0]; }
+    __device__ inline void push(const Frame& x)
+    {
+#pragma unroll
+        for (int i = K - 1; i > 0; --i) f[i] = f[i - 1];
+        f[0] = x;
+        depth += 1;
+    }
+    __device__ inline void pop()
+    {
+#pragma unroll
+        for (int i = 0; i < K - 1; ++i) f[i] = f[i + 1];
+        depth -= 1;
+    }
+};
+
+template <class Frame>
+struct ArrayFrames {
+    Frame f[kMaxDepthCap];
+    int depth = 0;
+    __device__ inline bool full() const { return false; }
+    __device__ inline Frame& top() { return f[depth - 1]; }
+    __device__ inline void push(const Frame& x) { f[depth++] = x; }
+    __device__ inline void pop() { depth -= 1; }
+};
 
 struct CrbdFrame {
     int remaining;
@@ -99,35 +138,37 @@ struct CrbdSim {
     // with probability rho; along its life it speciates Poisson(lambda * life)
     // times, and each daughter (born at a uniform time) must go undetected too.
     // Evaluated depth-first with an explicit frame stack; any detection, or
-    // exceeding the depth or event budget, answers "detected".
-    __device__ inline bool undetected(Stream& s, double t0)
+    // exceeding the depth or event budget, answers kDetected. kOverflow means
+    // the stack ran out of registers before any budget did (the caller then
+    // recomputes the particle with a deeper stack).
+    template <class Stack>
+    __device__ inline int undetected(Stream& s, double t0)
     {
-        CrbdFrame stack[kMaxDepthCap];
-        int depth = 0;
+        Stack stack;
         double enter_at = t0;
         bool entering = true;
         while (true) {
             if (entering) {
-                if (depth + 1 > max_depth) return false;
+                if (stack.depth + 1 > max_depth) return kDetected;
+                if (stack.full()) return kOverflow;
                 const double life = draw_exponential(s, mu);
                 if (life > enter_at) {
-                    if (draw_bernoulli(s, rho)) return false;
+                    if (draw_bernoulli(s, rho)) return kDetected;
                 }
                 const double len = life < enter_at ? life : enter_at;
                 const int n = draw_poisson(s, lambda * len);
-                if (n < 0) return false;
-                stack[depth] = CrbdFrame{n, enter_at, len};
-                depth += 1;
+                if (n < 0) return kDetected;
+                stack.push(CrbdFrame{n, enter_at, len});
                 entering = false;
             }
-            CrbdFrame& top = stack[depth - 1];
+            CrbdFrame& top = stack.top();
             if (top.remaining == 0) {
-                depth -= 1;
-                if (depth == 0) return true;
+                stack.pop();
+                if (stack.depth == 0) return kUndetected;
                 continue;
             }
             top.remaining -= 1;
-            if (events >= max_events) return false;
+            if (events >= max_events) return kDetected;
             events += 1;
             const double a = top.start - top.length;
             enter_at = draw_uniform(s, a, top.start);
@@ -142,8 +183,10 @@ struct Crbd {
     struct State {
         double lambda, mu;
     };
+    // Stack: frame stack for hidden lineages; overflow is set when it ran out.
+    template <class Stack>
     __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
-                                         Stream& s, bool& ckpt)
+                                         Stream& s, bool& ckpt, bool& overflow)
     {
         ckpt = true;
         if (b == 0) {
@@ -172,7 +215,12 @@ struct Crbd {
                 }
                 sim.events += 1;
                 const double t = draw_uniform(s, tc, tp);
-                if (!sim.undetected(s, t)) {
+                const int h = sim.template undetected<Stack>(s, t);
+                if (h == kOverflow) {
+                    overflow = true;
+                    return b;
+                }
+                if (h == kDetected) {
                     ln3 = -__builtin_huge_val();
                     break;
                 }
@@ -189,6 +237,11 @@ struct Crbd {
 // lineage rate lambda, eps, alpha, sigma, plus a stack of pending right-
 // daughter rates (its size is the same for every particle: sp_before[round]).
 // ---------------------------------------------------------------------------
+struct ClaDSPending {
+    double start, rate;
+    int depth;
+};
+
 struct ClaDSSide {
     double eps, log_alpha, sigma, rho;
     int events, max_events, max_depth;
@@ -198,33 +251,29 @@ struct ClaDSSide {
     // 1/(1+eps) (both daughters get r * LogNormal(log alpha, sigma)) and an
     // extinction otherwise; reaching the present is detection with prob. rho.
     // Depth-first: the second daughter waits on a stack while the first one's
-    // subtree is simulated.
-    struct Pending {
-        double start, rate;
-        int depth;
-    };
-    __device__ inline bool undetected(Stream& s, double t0, double r0)
+    // subtree is simulated. Returns kUndetected, kDetected or kOverflow.
+    template <class Stack>
+    __device__ inline int undetected(Stream& s, double t0, double r0)
     {
-        Pending stack[kMaxDepthCap];
-        int top = 0;
+        Stack stack;
         double start = t0, rate = r0;
         int depth = 1;
         while (true) {
             bool lineage_done = false;
-            if (depth > max_depth) return false;
-            if (events >= max_events) return false;
+            if (depth > max_depth) return kDetected;
+            if (events >= max_events) return kDetected;
             events += 1;
             const double w = draw_exponential(s, rate * (1.0 + eps));
             if (start - w <= 0.0) {
-                if (draw_bernoulli(s, rho)) return false;
+                if (draw_bernoulli(s, rho)) return kDetected;
                 lineage_done = true;
             } else {
                 const double t = start - w;
                 if (s.uniform() < 1.0 / (1.0 + eps)) {
+                    if (stack.full()) return kOverflow;
                     const double d1 = rate * draw_lognormal(s, log_alpha, sigma);
                     const double d2 = rate * draw_lognormal(s, log_alpha, sigma);
-                    stack[top] = Pending{t, d2, depth + 1};
-                    top += 1;
+                    stack.push(ClaDSPending{t, d2, depth + 1});
                     start = t;
                     rate = d1;
                     depth = depth + 1;
@@ -233,11 +282,12 @@ struct ClaDSSide {
                 }
             }
             if (lineage_done) {
-                if (top == 0) return true;
-                top -= 1;
-                start = stack[top].start;
-                rate = stack[top].rate;
-                depth = stack[top].depth;
+                if (stack.depth == 0) return kUndetected;
+                const ClaDSPending p = stack.top();
+                stack.pop();
+                start = p.start;
+                rate = p.rate;
+                depth = p.depth;
             }
         }
     }
@@ -256,8 +306,9 @@ struct Clads {
         uint64_t stride;  // particles per level
         uint32_t src, dst;
     };
+    template <class Stack>
     __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
-                                         Stream& s, bool& ckpt, const StackIO& io)
+                                         Stream& s, bool& ckpt, const StackIO& io, bool& overflow)
     {
         ckpt = true;
         if (b == 0) {
@@ -300,7 +351,12 @@ struct Clads {
             t = t - w;
             const double cont = lambda * draw_lognormal(s, log_alpha, st.sigma);
             const double sider = lambda * draw_lognormal(s, log_alpha, st.sigma);
-            if (!side.undetected(s, t, sider)) {
+            const int h = side.template undetected<Stack>(s, t, sider);
+            if (h == kOverflow) {
+                overflow = true;
+                return b;
+            }
+            if (h == kDetected) {
                 dead = true;
                 break;
             }

@@ -87,6 +87,7 @@ def lib():
         "smc_done": [vp, C.POINTER(i32)],
         "smc_log_z": [vp, C.POINTER(C.c_double)],
         "smc_run_to_end": [vp],
+        "smc_reset": [vp, u64],
         "smc_read": [vp, i32, vp, C.c_size_t],
         "smc_run_stats": [vp, C.POINTER(_Stats)],
         "smc_run_destroy": [vp],
@@ -258,6 +259,9 @@ class Run:
 
     def run_to_end(self):
         return _check(lib().smc_run_to_end(self._h), allow=(FINISHED, DEGENERATE))
+
+    def reset(self, seed: int):
+        _check(lib().smc_reset(self._h, int(seed)))
 
     def stats(self):
         s = _Stats()

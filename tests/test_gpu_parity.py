@@ -383,3 +383,50 @@ def test_crbd_full_size_sampled(smc, oracle, ctx):
     assert math.isfinite(s["log_z"])
     gpu.close()
     model.close()
+
+
+def test_graph_replays_match_eager_runs(smc, oracle, ctx):
+    """run_to_end replays one captured graph; each replay after a reset (with
+    eager runs and synchronisations in between) equals an eager run and the
+    oracle for that seed."""
+    tree = I.yule_tree(30, 77)
+    spec = I.crbd_spec(tree, precision=32)
+    model = smc.Model(ctx, spec)
+    replayed = smc.Run(model, 3000, 1)
+    for seed in (5, 6, 7, 5):
+        replayed.reset(seed)
+        assert replayed.run_to_end() == smc.FINISHED
+        eager = smc.Run(model, 3000, seed)
+        while True:
+            eager.step()
+            eager.resample()
+            done, st = eager.done()
+            if done:
+                break
+        ref = oracle.Run(spec, 3000, seed)
+        ref.run_to_end()
+        a, b = replayed.stats(), eager.stats()
+        assert a["log_z"] == b["log_z"] and a["block_steps"] == b["block_steps"] == ref.block_steps
+        assert abs(a["log_z"] - ref.log_z) <= LOGZ_RTOL * abs(ref.log_z)
+        assert np.array_equal(replayed.field(0, np.float32), eager.field(0, np.float32))
+        eager.close()
+    replayed.close()
+    model.close()
+
+
+def test_crbd_deep_recursion_matches(smc, oracle, ctx):
+    """Critical birth-death rates make hidden lineages recurse well past the
+    register-held frames, so many particles take the deep-stack pass."""
+    tree = I.yule_tree(8, 5)
+    say("crbd deep recursion fp64")
+    run_lockstep(smc, oracle, ctx, I.crbd_spec(tree, fixed_lambda=10.0, fixed_mu=10.0), 2048, 1)
+    say("crbd deep recursion fp32 priors")
+    run_lockstep(smc, oracle, ctx, I.crbd_spec(tree, precision=32, scale_lambda=8.0, scale_mu=8.0), 3000, 2)
+
+
+def test_clads_deep_side_lineages_match(smc, oracle, ctx):
+    tree = I.yule_tree(8, 6)
+    say("clads deep side lineages")
+    run_lockstep(smc, oracle, ctx, I.clads_spec(tree, precision=64, fixed_l0=8.0, fixed_eps=0.95, fixed_alpha=1.0,
+                                                fixed_sigma=0.0), 2048, 3)
+    run_lockstep(smc, oracle, ctx, I.clads_spec(tree, precision=32, fixed_l0=6.0, fixed_eps=0.9), 2048, 4)
