@@ -183,12 +183,13 @@ smc_status smc_run_destroy(smc_run* run); /* NULL-safe */
 
 /* Per-kernel timing with HIP events recorded on the context stream around
  * every launch a run makes while profiling is on (smc_step, smc_resample,
- * smc_run_to_end). Index 0 = propagation, 1 = reduction (log Z), 2 = scan and
- * ancestors; ms = summed durations, launches = count. smc_profile(run, 1)
+ * smc_run_to_end). Index 0 = propagation, 1 = deep-stack pass + fold of the
+ * propagation partials, 2 = reduction + fold (log Z, tile offsets), 3 = scan
+ * and ancestors; ms = summed durations, launches = count. smc_profile(run, 1)
  * clears previous records; both calls synchronise. */
 typedef struct {
-    double ms[3];
-    uint64_t launches[3];
+    double ms[4];
+    uint64_t launches[4];
 } smc_kernel_times;
 smc_status smc_profile(smc_run* run, int32_t enable);
 smc_status smc_profile_read(smc_run* run, smc_kernel_times* out);

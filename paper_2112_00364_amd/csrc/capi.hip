@@ -181,15 +181,20 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     h.lw = (double*)get(n * 8);
     h.anc = (uint32_t*)get(n * 4);
     if (m->kind == SMC_MODEL_CRBD || m->kind == SMC_MODEL_CLADS) h.deep_list = (uint32_t*)get(n * 4);
+    h.prop_tiles = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
+    h.part_key = (unsigned long long*)get(h.prop_tiles * 8);
+    h.part_cnt = (uint32_t*)get(h.prop_tiles * 4);
+    h.part_steps = (uint32_t*)get(h.prop_tiles * 4);
     h.part_q = (double*)get(h.red_tiles * 8);
     h.part_e = (double*)get(h.red_tiles * 8);
     h.prefix = (double*)get(h.red_tiles * 8);
     r->dev = (RunDev*)get(sizeof(RunDev));
-    r->n_prop = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
+    r->n_prop = h.prop_tiles;
     r->n_red = h.red_tiles;
     r->prop_tiles = (TileRef*)get(sizeof(TileRef) * r->n_prop);
     r->red_tiles = (TileRef*)get(sizeof(TileRef) * r->n_red);
-    bool ok = h.ctl && h.lw && h.anc && h.part_q && (h.deep_list || m->kind < SMC_MODEL_CRBD) && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
+    bool ok = h.ctl && h.lw && h.anc && h.part_q && (h.deep_list || m->kind < SMC_MODEL_CRBD) && h.part_key &&
+              h.part_cnt && h.part_steps && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
     for (int b = 0; b < 2; ++b) {
         ok = ok && h.buf[b].blk;
         for (int f = 0; f < real_fields(m->kind); ++f) ok = ok && h.buf[b].real[f];
@@ -220,13 +225,22 @@ smc_status do_step(smc_run* r)
     if (!r->expect_step) return fail(SMC_ERR_STATE, "smc_step called twice without smc_resample");
     if (r->known_status != SMC_OK) return r->known_status;
     hipStream_t st = r->ctx->stream;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (r->profiling && (a = r->next_event()) && (b = r->next_event())) HIP_TRY(hipEventRecord(a, st));
-    HIP_TRY(launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, st));
-    HIP_TRY(launch_propagate_deep(r->model->kind, r->model->precision, r->dev, 1, st));
-    if (a && b) {
+    const int kind = r->model->kind, prec = r->model->precision;
+    if (r->profiling) {
+        hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
+        if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
+        HIP_TRY(hipEventRecord(a, st));
+        HIP_TRY(launch_propagate(kind, prec, r->dev, r->prop_tiles, r->n_prop, st));
         HIP_TRY(hipEventRecord(b, st));
+        HIP_TRY(launch_propagate_deep(kind, prec, r->dev, 1, st));
+        HIP_TRY(launch_fold_max(r->dev, 1, st));
+        HIP_TRY(hipEventRecord(c, st));
         r->timed.push_back(smc_run::Timed{0, a, b});
+        r->timed.push_back(smc_run::Timed{1, b, c});
+    } else {
+        HIP_TRY(launch_propagate(kind, prec, r->dev, r->prop_tiles, r->n_prop, st));
+        HIP_TRY(launch_propagate_deep(kind, prec, r->dev, 1, st));
+        HIP_TRY(launch_fold_max(r->dev, 1, st));
     }
     r->expect_step = false;
     return SMC_OK;
@@ -241,14 +255,14 @@ smc_status do_resample(smc_run* r)
         hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
         if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
         HIP_TRY(hipEventRecord(a, st));
-        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, st));
+        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, 1, st));
         HIP_TRY(hipEventRecord(b, st));
         HIP_TRY(launch_scan_anc(r->dev, r->red_tiles, r->n_red, st));
         HIP_TRY(hipEventRecord(c, st));
-        r->timed.push_back(smc_run::Timed{1, a, b});
-        r->timed.push_back(smc_run::Timed{2, b, c});
+        r->timed.push_back(smc_run::Timed{2, a, b});
+        r->timed.push_back(smc_run::Timed{3, b, c});
     } else {
-        HIP_TRY(launch_resample(r->dev, r->red_tiles, r->n_red, st));
+        HIP_TRY(launch_resample(r->dev, r->red_tiles, r->n_red, 1, st));
     }
     r->expect_step = true;
     r->rounds_issued += 1;
@@ -458,7 +472,8 @@ static smc_status capture_run(smc_run* r, uint32_t rounds)
     for (uint32_t k = 0; k < rounds && e == hipSuccess; ++k) {
         e = launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, cap);
         if (e == hipSuccess) e = launch_propagate_deep(r->model->kind, r->model->precision, r->dev, 1, cap);
-        if (e == hipSuccess) e = launch_resample(r->dev, r->red_tiles, r->n_red, cap);
+        if (e == hipSuccess) e = launch_fold_max(r->dev, 1, cap);
+        if (e == hipSuccess) e = launch_resample(r->dev, r->red_tiles, r->n_red, 1, cap);
     }
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
@@ -663,28 +678,37 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     h.seed = seed;
     h.n = (uint32_t)n;
     h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
+    h.prop_tiles = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
     h.lw = const_cast<double*>(lw);
     h.anc = anc;
     h.ctl = (RunCtl*)arena.get(sizeof(RunCtl));
+    h.part_key = (unsigned long long*)arena.get(h.prop_tiles * 8);
+    h.part_cnt = (uint32_t*)arena.get(h.prop_tiles * 4);
+    h.part_steps = (uint32_t*)arena.get(h.prop_tiles * 4);
     h.part_q = (double*)arena.get(h.red_tiles * 8);
     h.part_e = (double*)arena.get(h.red_tiles * 8);
     h.prefix = (double*)arena.get(h.red_tiles * 8);
     RunDev* dev = (RunDev*)arena.get(sizeof(RunDev));
     TileRef* tiles = (TileRef*)arena.get(sizeof(TileRef) * h.red_tiles);
-    if (!h.ctl || !h.part_q || !h.part_e || !h.prefix || !dev || !tiles) {
+    TileRef* ptiles = (TileRef*)arena.get(sizeof(TileRef) * h.prop_tiles);
+    if (!h.ctl || !h.part_key || !h.part_cnt || !h.part_steps || !h.part_q || !h.part_e || !h.prefix || !dev ||
+        !tiles || !ptiles) {
         arena.release_all();
         return fail(SMC_ERR_OOM, "device allocation failed");
     }
-    std::vector<TileRef> th(h.red_tiles);
+    std::vector<TileRef> th(h.red_tiles), ph(h.prop_tiles);
     for (uint32_t t = 0; t < h.red_tiles; ++t) th[t] = TileRef{0, t};
+    for (uint32_t t = 0; t < h.prop_tiles; ++t) ph[t] = TileRef{0, t};
     RunCtl c0{};
     c0.round = round;
     hipStream_t st = ctx->stream;
     hipError_t e = hipMemcpyAsync(h.ctl, &c0, sizeof(RunCtl), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dev, &h, sizeof(RunDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(tiles, th.data(), sizeof(TileRef) * th.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_maxkey(dev, tiles, h.red_tiles, st);
-    if (e == hipSuccess) e = launch_resample(dev, tiles, h.red_tiles, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(ptiles, ph.data(), sizeof(TileRef) * ph.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_maxkey(dev, ptiles, h.prop_tiles, st);
+    if (e == hipSuccess) e = launch_fold_max(dev, 1, st);
+    if (e == hipSuccess) e = launch_resample(dev, tiles, h.red_tiles, 1, st);
     if (e == hipSuccess) e = hipMemcpyAsync(logz_inc, &h.ctl->log_z, sizeof(double), hipMemcpyDeviceToDevice, st);
     RunCtl c{};
     if (e == hipSuccess) e = hipMemcpyAsync(&c, h.ctl, sizeof(RunCtl), hipMemcpyDeviceToHost, st);
@@ -815,9 +839,10 @@ smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
     hipStream_t st = b->ctx->stream;
     for (int32_t k = 0; k < rounds; ++k) {
         for (const auto& g : b->groups) HIP_TRY(launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, st));
-        for (const auto& g : b->groups)
-            HIP_TRY(launch_propagate_deep(g.kind, g.precision, b->runs, (uint32_t)b->runs_h.size(), st));
-        HIP_TRY(launch_resample(b->runs, b->red_tiles, b->n_red, st));
+        const uint32_t n_runs = (uint32_t)b->runs_h.size();
+        for (const auto& g : b->groups) HIP_TRY(launch_propagate_deep(g.kind, g.precision, b->runs, n_runs, st));
+        HIP_TRY(launch_fold_max(b->runs, n_runs, st));
+        HIP_TRY(launch_resample(b->runs, b->red_tiles, b->n_red, n_runs, st));
     }
     for (smc_run* r : b->slots)
         if (r) r->rounds_issued += (uint32_t)rounds;

@@ -7,8 +7,8 @@ namespace pcfg {
 
 // Per-run control block in device memory. Kernels read the round and status
 // from here, so a fixed launch sequence can be replayed without host input.
-struct alignas(64) RunCtl {
-    unsigned long long maxkey;       // order-preserving key of max lw this round (0 = none yet)
+struct alignas(128) RunCtl {
+    unsigned long long maxkey;       // order-preserving key of max lw this round (0 = none)
     unsigned long long block_steps;  // canonical block executions so far
     double log_z;                    // running normalising-constant estimate
     double m_cur;                    // M of the pending resampling
@@ -18,11 +18,12 @@ struct alignas(64) RunCtl {
     int32_t status;                  // SMC_OK / FINISHED / ERR_NAN / DEGENERATE
     uint32_t active;                 // particles not at b_stop after this round's propagation
     uint32_t bad;                    // a NaN or +inf log-weight was produced
-    uint32_t ticket;                 // work-groups done in the reduction
     uint32_t deep_count;             // particles handed to the deep-stack pass this round
-    uint32_t pad[3];
+    // partials of the deep-stack pass (one per deep work-group)
+    unsigned long long deep_key[4];
+    uint32_t deep_cnt[4];            // active | bad << 31
+    uint32_t deep_steps[4];
 };
-
 // One particle buffer: block index, real fields (storage precision), int
 // fields, and the ClaDS stack (level-major: level k of particle j at k*n + j).
 struct ParticleBuf {
@@ -42,6 +43,10 @@ struct RunDev {
     double* lw;
     uint32_t* anc;
     uint32_t* deep_list; // particles whose hidden-lineage stack outgrew the registers
+    uint32_t prop_tiles; // propagation tiles of kPropThreads particles
+    unsigned long long* part_key;  // per propagation tile: max key
+    uint32_t* part_cnt;            // per propagation tile: active count | bad << 31
+    uint32_t* part_steps;          // per propagation tile: block steps
     double* part_q;      // per reduction tile: sum of grid units
     double* part_e;      // per reduction tile: sum of exp(lw - M)
     double* prefix;      // per reduction tile: grid units before the tile

@@ -84,15 +84,6 @@ __device__ inline uint32_t offspring_before(double W, double Qtot, uint32_t U, u
     return c;
 }
 
-// Device-scope load that bypasses non-coherent caches: partials written by
-// work-groups on other XCDs (each XCD has its own L2) after a release fence.
-__device__ inline double coherent_load(const double* p)
-{
-    const unsigned long long v =
-        __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)v);
-}
-
 template <class T>
 __device__ inline T wave_sum(T v)
 {
@@ -265,10 +256,10 @@ __global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __rest
             a += s_act[w];
             st += s_steps[w];
         }
-        if (k) atomicMax(&ctl->maxkey, k);
-        if (b) atomicOr(&ctl->bad, 1u);
-        if (a) atomicAdd(&ctl->active, a);
-        if (st) atomicAdd(&ctl->block_steps, (unsigned long long)st);
+        // per-tile partials, folded by k_fold_max (no same-address atomics)
+        R.part_key[tr.tile] = k;
+        R.part_cnt[tr.tile] = a | (b ? 0x80000000u : 0u);
+        R.part_steps[tr.tile] = st;
     }
 }
 
@@ -284,18 +275,109 @@ __global__ __launch_bounds__(kPropThreads) void k_propagate_deep(const RunDev* _
     RunCtl* ctl = R.ctl;
     if (ctl->status != 0 || R.model->kind != Kind || R.model->precision != (int)(8 * sizeof(Real))) return;
     const uint32_t count = ctl->deep_count;
+    if (count == 0) return;  // uniform: k_fold_max ignores the deep partials then
     const uint32_t round = ctl->round;
-    const uint32_t first = (blockIdx.x % kDeepGroups) * kPropThreads + threadIdx.x;
-    for (uint32_t i = first; i < count; i += kDeepGroups * kPropThreads) {
+    const uint32_t g = blockIdx.x % kDeepGroups;
+    unsigned long long key = 0;
+    uint32_t bad = 0, act = 0, steps_all = 0;
+    for (uint32_t i = g * kPropThreads + threadIdx.x; i < count; i += kDeepGroups * kPropThreads) {
         const uint32_t j = R.deep_list[i];
         uint8_t blk;
         double lw;
         uint32_t steps;
         run_particle<Kind, Real, false>(R, *R.model, j, round, blk, lw, steps);
-        if (lw != lw || lw == __builtin_huge_val()) atomicOr(&ctl->bad, 1u);
-        else atomicMax(&ctl->maxkey, order_key(lw));
-        if (blk != kStop) atomicAdd(&ctl->active, 1u);
-        atomicAdd(&ctl->block_steps, (unsigned long long)steps);
+        if (lw != lw || lw == __builtin_huge_val()) bad = 1;
+        else {
+            const unsigned long long kk = order_key(lw);
+            key = kk > key ? kk : key;
+        }
+        act += blk != kStop ? 1u : 0u;
+        steps_all += steps;
+    }
+    key = wave_max_u64(key);
+    bad = wave_sum(bad);
+    act = wave_sum(act);
+    steps_all = wave_sum(steps_all);
+    __shared__ unsigned long long s_key[kPropThreads / 64];
+    __shared__ uint32_t s_bad[kPropThreads / 64], s_act[kPropThreads / 64], s_steps[kPropThreads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        s_key[wave] = key;
+        s_bad[wave] = bad;
+        s_act[wave] = act;
+        s_steps[wave] = steps_all;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long k = s_key[0];
+        uint32_t b = s_bad[0], a = s_act[0], st = s_steps[0];
+        for (int w = 1; w < kPropThreads / 64; ++w) {
+            k = s_key[w] > k ? s_key[w] : k;
+            b += s_bad[w];
+            a += s_act[w];
+            st += s_steps[w];
+        }
+        ctl->deep_key[g] = k;
+        ctl->deep_cnt[g] = a | (b ? 0x80000000u : 0u);
+        ctl->deep_steps[g] = st;
+    }
+}
+
+// One work-group per run folds the propagation partials: M (as a key), the
+// NaN flag, the number of active particles and the block steps of the round.
+constexpr int kFoldThreads = 1024;
+
+__global__ __launch_bounds__(kFoldThreads) void k_fold_max(const RunDev* __restrict__ runs)
+{
+    const RunDev& R = runs[blockIdx.x];
+    RunCtl* ctl = R.ctl;
+    if (ctl->status != 0) return;
+    unsigned long long key = 0;
+    uint32_t bad = 0, act = 0, steps = 0;
+    for (uint32_t t = threadIdx.x; t < R.prop_tiles; t += kFoldThreads) {
+        const unsigned long long k = R.part_key[t];
+        const uint32_t c = R.part_cnt[t];
+        key = k > key ? k : key;
+        act += c & 0x7fffffffu;
+        bad |= c >> 31;
+        steps += R.part_steps[t];
+    }
+    if (ctl->deep_count > 0 && threadIdx.x < kDeepGroups) {
+        const unsigned long long k = ctl->deep_key[threadIdx.x];
+        const uint32_t c = ctl->deep_cnt[threadIdx.x];
+        key = k > key ? k : key;
+        act += c & 0x7fffffffu;
+        bad |= c >> 31;
+        steps += ctl->deep_steps[threadIdx.x];
+    }
+    key = wave_max_u64(key);
+    bad = wave_sum(bad);
+    act = wave_sum(act);
+    steps = wave_sum(steps);
+    __shared__ unsigned long long s_key[kFoldThreads / 64];
+    __shared__ uint32_t s_bad[kFoldThreads / 64], s_act[kFoldThreads / 64], s_steps[kFoldThreads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        s_key[wave] = key;
+        s_bad[wave] = bad;
+        s_act[wave] = act;
+        s_steps[wave] = steps;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long k = 0;
+        uint32_t b = 0, a = 0;
+        unsigned long long st = 0;
+        for (int w = 0; w < kFoldThreads / 64; ++w) {
+            k = s_key[w] > k ? s_key[w] : k;
+            b += s_bad[w];
+            a += s_act[w];
+            st += s_steps[w];
+        }
+        ctl->maxkey = k;
+        ctl->bad = b ? 1u : 0u;
+        ctl->active = a;
+        ctl->block_steps += st;
     }
 }
 
@@ -307,30 +389,25 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
 {
     const TileRef tr = tiles[blockIdx.x];
     const RunDev& R = runs[tr.run];
-    RunCtl* ctl = R.ctl;
-    if (ctl->status != 0) return;
-    const bool bad = ctl->bad != 0;
+    const RunCtl* ctl = R.ctl;
+    if (ctl->status != 0 || ctl->bad != 0) return;
     const double M = key_value(ctl->maxkey);
-    const bool usable = !bad && ctl->maxkey != 0 && M != -__builtin_huge_val();
+    if (ctl->maxkey == 0 || M == -__builtin_huge_val()) return;
     const double scale = (double)(1ull << grid_bits(R.n));
-
     double sq = 0.0, se = 0.0;
-    if (usable) {
-        const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
+    const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
 #pragma unroll
-        for (int k = 0; k < kRedItems; ++k) {
-            const uint32_t i = base + k;
-            if (i < R.n) {
-                const double e = fn::exp(R.lw[i] - M);
-                se += e;
-                sq += __builtin_rint(e * scale);
-            }
+    for (int k = 0; k < kRedItems; ++k) {
+        const uint32_t i = base + k;
+        if (i < R.n) {
+            const double e = fn::exp(R.lw[i] - M);
+            se += e;
+            sq += __builtin_rint(e * scale);
         }
     }
     sq = wave_sum(sq);
     se = wave_sum(se);
     __shared__ double s_q[kRedThreads / 64], s_e[kRedThreads / 64];
-    __shared__ bool s_last;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) {
         s_q[wave] = sq;
@@ -345,37 +422,31 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
         }
         R.part_q[tr.tile] = q;
         R.part_e[tr.tile] = e;
-        __threadfence();
-        const uint32_t t = atomicAdd(&ctl->ticket, 1u);
-        s_last = (t == R.red_tiles - 1);
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
+}
 
-    // Last work-group of this run: fold the tile partials (fixed order) and
-    // write each tile's exclusive offset in grid units (exact in FP64).
+// One work-group per run: fold the tile sums in tile order, write each tile's
+// exclusive offset in grid units (exact in FP64), update log Z (Sec. 3.3),
+// decide termination and draw the round's resampling offset word.
+__global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __restrict__ runs)
+{
+    const RunDev& R = runs[blockIdx.x];
+    RunCtl* ctl = R.ctl;
+    if (ctl->status != 0) return;
+    const bool bad = ctl->bad != 0;
+    const double M = key_value(ctl->maxkey);
+    const bool usable = !bad && ctl->maxkey != 0 && M != -__builtin_huge_val();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t T = R.red_tiles;
-    const uint32_t per = (T + kRedThreads - 1) / kRedThreads;
+    const uint32_t per = (T + kFoldThreads - 1) / kFoldThreads;
     const uint32_t t0 = threadIdx.x * per;
     const uint32_t t1 = t0 + per < T ? t0 + per : T;
-    // loads issued in batches of kBatch independent requests (one latency each)
-    constexpr int kBatch = 8;
     double q_local = 0.0, e_local = 0.0;
-    for (uint32_t base = t0; base < t1; base += kBatch) {
-        double qb[kBatch], eb[kBatch];
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            const bool in = base + k < t1;
-            qb[k] = in ? coherent_load(&R.part_q[base + k]) : 0.0;
-            eb[k] = in ? coherent_load(&R.part_e[base + k]) : 0.0;
+    if (usable)
+        for (uint32_t t = t0; t < t1; ++t) {
+            q_local += R.part_q[t];
+            e_local += R.part_e[t];
         }
-#pragma unroll
-        for (int k = 0; k < kBatch; ++k) {
-            q_local += qb[k];
-            e_local += eb[k];
-        }
-    }
     double q_incl = q_local;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -383,27 +454,21 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
         if (lane >= off) q_incl += o;
     }
     const double e_wave = wave_sum(e_local);
-    __shared__ double s_qw[kRedThreads / 64];
+    __shared__ double s_qw[kFoldThreads / 64], s_ew[kFoldThreads / 64];
     if (lane == 63) s_qw[wave] = q_incl;
-    if (lane == 0) s_e[wave] = e_wave;
+    if (lane == 0) s_ew[wave] = e_wave;
     __syncthreads();
     double q_before = 0.0, q_all = 0.0, e_all = 0.0;
-    for (int w = 0; w < kRedThreads / 64; ++w) {
+    for (int w = 0; w < kFoldThreads / 64; ++w) {
         if (w < wave) q_before += s_qw[w];
         q_all += s_qw[w];
-        e_all += s_e[w];
+        e_all += s_ew[w];
     }
-    {
+    if (usable) {
         double run = q_before + (q_incl - q_local);
-        for (uint32_t base = t0; base < t1; base += kBatch) {
-            double qb[kBatch];
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) qb[k] = base + k < t1 ? coherent_load(&R.part_q[base + k]) : 0.0;
-#pragma unroll
-            for (int k = 0; k < kBatch; ++k) {
-                if (base + k < t1) R.prefix[base + k] = run;
-                run += qb[k];
-            }
+        for (uint32_t t = t0; t < t1; ++t) {
+            R.prefix[t] = run;
+            run += R.part_q[t];
         }
     }
     if (threadIdx.x == 0) {
@@ -414,8 +479,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
             ctl->log_z = -__builtin_huge_val();
             ctl->status = -6;  // SMC_DEGENERATE
         } else {
-            const double S = e_all;
-            ctl->log_z = ctl->log_z + ((M + fn::log(S)) - fn::log((double)R.n));
+            ctl->log_z = ctl->log_z + ((M + fn::log(e_all)) - fn::log((double)R.n));
             if (ctl->active == 0) {
                 ctl->status = 1;  // SMC_FINISHED
             } else {
@@ -425,12 +489,7 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
                 ctl->round = round + 1;
             }
         }
-        ctl->maxkey = 0;
-        ctl->active = 0;
-        ctl->bad = 0;
-        ctl->ticket = 0;
         ctl->deep_count = 0;
-        __threadfence();
     }
 }
 
@@ -501,31 +560,39 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
 // ---------------------------------------------------------------------------
 // Standalone pieces: max of a given weight vector, reads, self-tests.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRedThreads) void k_maxkey(const RunDev* __restrict__ runs,
-                                                         const TileRef* __restrict__ tiles)
+__global__ __launch_bounds__(kPropThreads) void k_maxkey(const RunDev* __restrict__ runs,
+                                                          const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
     const RunDev& R = runs[tr.run];
+    const uint32_t i = tr.tile * kPropThreads + threadIdx.x;
     unsigned long long key = 0;
     uint32_t bad = 0;
-    const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
-    for (int k = 0; k < kRedItems; ++k) {
-        const uint32_t i = base + k;
-        if (i < R.n) {
-            const double x = R.lw[i];
-            if (x != x || x == __builtin_huge_val()) bad = 1;
-            else {
-                const unsigned long long kk = order_key(x);
-                key = kk > key ? kk : key;
-            }
-        }
+    if (i < R.n) {
+        const double x = R.lw[i];
+        if (x != x || x == __builtin_huge_val()) bad = 1;
+        else key = order_key(x);
     }
     key = wave_max_u64(key);
     bad = wave_sum(bad);
-    if ((threadIdx.x & 63) == 0) {
-        if (key) atomicMax(&R.ctl->maxkey, key);
-        if (bad) atomicOr(&R.ctl->bad, 1u);
-        atomicAdd(&R.ctl->active, 1u);  // standalone resampling always resamples
+    __shared__ unsigned long long s_key[kPropThreads / 64];
+    __shared__ uint32_t s_bad[kPropThreads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        s_key[wave] = key;
+        s_bad[wave] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long k = 0;
+        uint32_t b = 0;
+        for (int w = 0; w < kPropThreads / 64; ++w) {
+            k = s_key[w] > k ? s_key[w] : k;
+            b += s_bad[w];
+        }
+        R.part_key[tr.tile] = k;
+        R.part_cnt[tr.tile] = 1u | (b ? 0x80000000u : 0u);  // standalone resampling always resamples
+        R.part_steps[tr.tile] = 0;
     }
 }
 
@@ -594,7 +661,6 @@ __global__ void k_reset(RunDev* run, uint64_t seed)
     c->status = 0;
     c->active = 0;
     c->bad = 0;
-    c->ticket = 0;
     c->deep_count = 0;
 }
 
@@ -648,10 +714,18 @@ hipError_t launch_propagate_deep(int kind, int precision, const RunDev* runs, ui
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
+hipError_t launch_fold_max(const RunDev* runs, uint32_t n_runs, hipStream_t st)
+{
+    if (n_runs == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fold_max, dim3(n_runs), dim3(kFoldThreads), 0, st, runs);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce, dim3(n_tiles), dim3(kRedThreads), 0, st, runs, tiles);
+    hipLaunchKernelGGL(k_fold_sums, dim3(n_runs), dim3(kFoldThreads), 0, st, runs);
     return hipGetLastError();
 }
 
@@ -662,16 +736,16 @@ hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_
     return hipGetLastError();
 }
 
-hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
+hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs, hipStream_t st)
 {
-    hipError_t e = launch_reduce(runs, tiles, n_tiles, st);
+    hipError_t e = launch_reduce(runs, tiles, n_tiles, n_runs, st);
     if (e != hipSuccess) return e;
     return launch_scan_anc(runs, tiles, n_tiles, st);
 }
 
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_maxkey, dim3(n_tiles), dim3(kRedThreads), 0, st, runs, tiles);
+    hipLaunchKernelGGL(k_maxkey, dim3(n_tiles), dim3(kPropThreads), 0, st, runs, tiles);
     return hipGetLastError();
 }
 

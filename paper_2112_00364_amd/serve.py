@@ -1,0 +1,141 @@
+"""Serving loop: continuous batching of SMC inference requests on one GPU.
+
+Requests (a model specification, a particle count and a seed) arrive over
+time. The server admits a request when its particle memory fits the budget,
+adds it to the device-resident batch (smc_batch_add), advances every live run
+by a few rounds per tick (one launch per kernel for all runs), retires runs as
+they finish and records latency = completion - arrival. The one-at-a-time
+baseline serves the same requests first-come first-served, each as a plain
+smc_init + smc_run_to_end on the same kernels.
+
+All SMC work runs in libpcfgsmc.so; this module is host-side scheduling only.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import smc
+
+
+def footprint_bytes(kind: str, n: int, precision: int, stack_depth: int = 0) -> int:
+    """Device bytes of one run: double-buffered block + state (+ ClaDS stack),
+    log-weights, ancestors, deep list, tile partials."""
+    real = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4}[kind]
+    rb = 4 if precision == 32 else 8
+    per = 2 * (1 + real * rb + (stack_depth * rb if kind == "clads" else 0)) + 8 + 4 + 4
+    tiles = (n + 255) // 256
+    return n * per + tiles * 16 + (n + 1023) // 1024 * 24 + 512
+
+
+def clads_stack_depth(tree) -> int:
+    cur = deepest = 1
+    left = tree["left"]
+    for node in range(1, len(left)):
+        cur = cur + 1 if left[node] >= 0 else max(cur - 1, 0)
+        deepest = max(deepest, cur)
+    return deepest + 1
+
+
+def make_requests(n_requests: int, seed: int, rate_per_s: float, precision: int = 32):
+    """The serving workload with its trees built up front (inputs, not serving work)."""
+    reqs = I.request_stream(n_requests, seed, rate_per_s)
+    for r in reqs:
+        tree = I.yule_tree(r["tips"], r["tree_seed"])
+        if r["kind"] == "crbd":
+            r["spec"] = I.crbd_spec(tree, precision=precision)
+            r["depth"] = 0
+        else:
+            r["spec"] = I.clads_spec(tree, precision=precision)
+            r["depth"] = clads_stack_depth(tree)
+        r["rounds"] = 2 * r["tips"] - 1
+        r["block_steps"] = r["n"] * r["rounds"]
+        r["bytes"] = footprint_bytes(r["kind"], r["n"], precision, r["depth"])
+    return reqs
+
+
+def rescale_arrivals(reqs, rate_per_s: float, seed: int):
+    """Same requests, Poisson arrivals at a new rate."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    for r in reqs:
+        t += rng.exponential(1.0 / rate_per_s)
+        r["arrival"] = t
+    return reqs
+
+
+def serve_one_at_a_time(ctx: smc.Context, reqs, honour_arrivals=True):
+    """FIFO, one plain run at a time."""
+    import torch
+    out = []
+    t0 = time.perf_counter()
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if honour_arrivals and r["arrival"] > now:
+            time.sleep(r["arrival"] - now)
+        start = time.perf_counter() - t0
+        model = smc.Model(ctx, r["spec"])
+        run = smc.Run(model, r["n"], r["seed"])
+        st = run.run_to_end()
+        lz = run.log_z()
+        done = time.perf_counter() - t0
+        steps = run.stats()["block_steps"]
+        run.close()
+        model.close()
+        out.append({"id": r["id"], "arrival": r["arrival"], "start": start, "done": done, "log_z": lz,
+                    "status": st, "block_steps": steps})
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: int = 8,
+                  max_live: int = 256, honour_arrivals=True):
+    """Continuous batching: admit while memory and slots allow, tick, retire."""
+    pending = collections.deque(sorted(reqs, key=lambda r: r["arrival"]))
+    batch = smc.Batch(ctx)
+    live = {}       # slot -> (request, model, admitted time)
+    used = 0
+    out = []
+    t0 = time.perf_counter()
+    while pending or live:
+        now = time.perf_counter() - t0
+        # admission: arrived requests in order while their particle memory fits
+        while pending and (not honour_arrivals or pending[0]["arrival"] <= now):
+            r = pending[0]
+            if live and (used + r["bytes"] > memory_budget or len(live) >= max_live):
+                break
+            pending.popleft()
+            model = smc.Model(ctx, r["spec"])
+            slot = batch.add(model, r["n"], r["seed"])
+            live[slot] = (r, model, time.perf_counter() - t0)
+            used += r["bytes"]
+        if not live:
+            if pending:
+                time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
+            continue
+        batch.tick(rounds_per_tick)
+        done, lz, st, steps = batch.poll()
+        now = time.perf_counter() - t0
+        for slot in list(live):
+            if done[slot]:
+                r, model, admitted = live.pop(slot)
+                out.append({"id": r["id"], "arrival": r["arrival"], "start": admitted, "done": now,
+                            "log_z": float(lz[slot]), "status": int(st[slot]), "block_steps": int(steps[slot])})
+                batch.retire(slot)
+                model.close()
+                used -= r["bytes"]
+    batch.close()
+    return out, time.perf_counter() - t0
+
+
+def summarize(results, makespan: float) -> dict:
+    lat = np.array([r["done"] - r["arrival"] for r in results])
+    steps = sum(r["block_steps"] for r in results)
+    return {"requests": len(results), "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
+            "makespan_s": makespan, "block_steps": int(steps), "block_steps_per_s": steps / makespan,
+            "failed": int(sum(1 for r in results if r["status"] != smc.FINISHED))}

@@ -54,7 +54,7 @@ class _Stats(C.Structure):
 
 
 class _KernelTimes(C.Structure):
-    _fields_ = [("ms", C.c_double * 3), ("launches", C.c_uint64 * 3)]
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_uint64 * 4)]
 
 
 _ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t)
@@ -273,11 +273,11 @@ class Run:
         _check(lib().smc_profile(self._h, 1 if enable else 0))
 
     def kernel_times(self):
-        """{kernel: (total ms, launches)} for propagate, reduce, scan_anc."""
+        """{kernel: (total ms, launches)} for propagate, deep+fold_max, reduce+fold_sums, scan_anc."""
         t = _KernelTimes()
         _check(lib().smc_profile_read(self._h, C.byref(t)))
-        names = ("propagate", "reduce", "scan_anc")
-        return {names[i]: (t.ms[i], int(t.launches[i])) for i in range(3)}
+        names = ("propagate", "deep_fold", "reduce", "scan_anc")
+        return {names[i]: (t.ms[i], int(t.launches[i])) for i in range(4)}
 
     def _read(self, what, dtype, count=1):
         out = np.zeros(self.n * count, dtype=dtype)
