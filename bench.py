@@ -78,6 +78,62 @@ def cpu_baseline(spec, n: int):
                       f"single thread, {dt:.1f} s"}
 
 
+def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16):
+    """512 independent ClaDS runs (trees of 32-128 tips, seeds 4000 + r), 4096
+    particles each, advanced together by the batch API."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(4000)
+    tips = rng.integers(32, 129, size=runs)
+    models = [smc.Model(ctx, I.clads_spec(I.yule_tree(int(t), 4000 + r), precision=32)) for r, t in enumerate(tips)]
+    b = smc.Batch(ctx)
+    for r, m in enumerate(models):
+        b.add(m, n, 40000 + r)
+    b.tick(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ticks = 0
+    while True:
+        b.tick(rounds_per_tick)
+        ticks += 1
+        done, lz, st, steps = b.poll()
+        if ticks % 4 == 0:
+            print(f"batched: tick {ticks}, {int(done.sum())}/{runs} done", file=sys.stderr, flush=True)
+        if done.all():
+            break
+    dt = time.perf_counter() - t0
+    total = int(steps.sum())
+    ok = int((st == smc.FINISHED).sum())
+    b.close()
+    for m in models:
+        m.close()
+    return {"workload": f"clads_batch_{runs}x{n}", "runs": runs, "particles_per_run": n,
+            "tips": [int(tips.min()), int(tips.max())], "seconds": dt, "block_steps": total,
+            "block_steps_per_s": total / dt, "finished_runs": ok, "rounds_per_tick": rounds_per_tick}
+
+
+def serving(ctx, smc, n_requests: int, budget_bytes: int):
+    """Serving stream: calibrate the one-at-a-time service rate, then replay the
+    same requests with Poisson arrivals at 0.9 x that rate through (a) FIFO
+    one-at-a-time plain runs and (b) continuous batching."""
+    from paper_2112_00364_amd import serve as S
+    reqs = S.make_requests(n_requests, 5000, rate_per_s=1.0)
+    calib = reqs[: min(32, len(reqs))]
+    _, t_cal = S.serve_one_at_a_time(ctx, calib, honour_arrivals=False)
+    rate = len(calib) / t_cal
+    arr = 0.9 * rate
+    S.rescale_arrivals(reqs, arr, 5001)
+    print(f"serving: one-at-a-time rate {rate:.2f}/s, arrivals at {arr:.2f}/s", file=sys.stderr, flush=True)
+    base, t_base = S.serve_one_at_a_time(ctx, reqs)
+    bat, t_bat = S.serve_batched(ctx, reqs, budget_bytes)
+    sb, sbb = S.summarize(base, t_base), S.summarize(bat, t_bat)
+    same = {r["id"]: r["log_z"] for r in base}
+    worst = max(abs(r["log_z"] - same[r["id"]]) / max(1.0, abs(same[r["id"]])) for r in bat)
+    return {"requests": n_requests, "arrival_rate_per_s": arr, "one_at_a_time_service_rate_per_s": rate,
+            "one_at_a_time": sb, "batched": sbb, "max_rel_logz_diff_batched_vs_alone": worst,
+            "memory_budget_bytes": budget_bytes}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +143,9 @@ def main():
                     help="particles in the CPU oracle's bounded sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-run batched ClaDS leg")
+    ap.add_argument("--serving-requests", type=int, default=2000, help="0 skips the serving leg")
+    ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -149,6 +208,8 @@ def main():
         prof.close()
         kernels = {}
         for k, (ms, launches) in times.items():
+            if launches == 0:
+                continue
             avg_ms = ms / launches
             b = bytes_per_launch(k, N_PARTICLES, rounds)
             kernels[k] = {"avg_us": avg_ms * 1e3, "launches": launches, "alg_bytes_per_launch": b,
@@ -181,7 +242,14 @@ def main():
         "wall_s_timed": wall,
         "log_z": log_zs,
     }
+    if not args.no_batched:
+        print("batched leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_clads(ctx, smc, I)
+    if args.serving_requests > 0:
+        print("serving leg", file=sys.stderr, flush=True)
+        out["serving"] = serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30))
     if not args.no_cpu_baseline:
+        print("cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_particles)
     print(json.dumps(out))
     model.close()

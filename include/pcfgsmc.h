@@ -150,13 +150,16 @@ smc_status smc_done(smc_run* run, int32_t* done);
 smc_status smc_log_z(smc_run* run, double* out);
 
 /* Step and resample until the run ends. For models whose particles advance in
- * lockstep (LGSSM, CRBD, CLADS) a run starting at round 0 replays one captured
- * HIP graph of all its rounds (captured on the first call); otherwise it checks
- * termination every 16 rounds. Returns SMC_FINISHED or the failure status. */
+ * lockstep (LGSSM, CRBD, CLADS) all rounds are enqueued before one termination
+ * check; once a run has been reset (smc_reset), its rounds are captured into
+ * one HIP graph and every later run of it replays that graph. Other models
+ * check termination every 16 rounds. Returns SMC_FINISHED or the failure
+ * status. */
 smc_status smc_run_to_end(smc_run* run);
 
 /* Algorithm 1 step 1 again on the run's existing buffers, with a new seed:
- * no allocation; the next smc_run_to_end replays the captured graph. */
+ * no allocation; the next smc_run_to_end replays (capturing it the first time)
+ * a graph of all rounds. */
 smc_status smc_reset(smc_run* run, uint64_t seed);
 
 /* Copy per-particle data to a caller-owned host buffer (synchronises).

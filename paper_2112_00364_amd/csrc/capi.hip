@@ -127,6 +127,7 @@ struct smc_run {
     // the whole lockstep run (rounds 0..R-1) captured once and replayed
     hipGraphExec_t graph = nullptr;
     uint32_t graph_rounds = 0;
+    uint32_t resets = 0;  // a reset run is replayed from a captured graph
     hipEvent_t next_event()
     {
         if (events_used == event_pool.size()) {
@@ -180,8 +181,9 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     }
     h.lw = (double*)get(n * 8);
     h.anc = (uint32_t*)get(n * 4);
-    if (m->kind == SMC_MODEL_CRBD || m->kind == SMC_MODEL_CLADS) h.deep_list = (uint32_t*)get(n * 4);
     h.prop_tiles = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
+    h.fused = h.prop_tiles <= kMaxFusedPropTiles ? 1u : 0u;
+    if (m->kind == SMC_MODEL_CLADS) h.side_stack = get((size_t)kMaxDepthCap * n * 17);
     h.part_key = (unsigned long long*)get(h.prop_tiles * 8);
     h.part_cnt = (uint32_t*)get(h.prop_tiles * 4);
     h.part_steps = (uint32_t*)get(h.prop_tiles * 4);
@@ -193,8 +195,8 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     r->n_red = h.red_tiles;
     r->prop_tiles = (TileRef*)get(sizeof(TileRef) * r->n_prop);
     r->red_tiles = (TileRef*)get(sizeof(TileRef) * r->n_red);
-    bool ok = h.ctl && h.lw && h.anc && h.part_q && (h.deep_list || m->kind < SMC_MODEL_CRBD) && h.part_key &&
-              h.part_cnt && h.part_steps && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
+    bool ok = h.ctl && h.lw && h.anc && h.part_q && h.part_key && h.part_cnt && h.part_steps &&
+              (h.side_stack || m->kind != SMC_MODEL_CLADS) && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
     for (int b = 0; b < 2; ++b) {
         ok = ok && h.buf[b].blk;
         for (int f = 0; f < real_fields(m->kind); ++f) ok = ok && h.buf[b].real[f];
@@ -226,21 +228,20 @@ smc_status do_step(smc_run* r)
     if (r->known_status != SMC_OK) return r->known_status;
     hipStream_t st = r->ctx->stream;
     const int kind = r->model->kind, prec = r->model->precision;
+    const bool fused = r->host.fused != 0;
     if (r->profiling) {
         hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
         if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
         HIP_TRY(hipEventRecord(a, st));
         HIP_TRY(launch_propagate(kind, prec, r->dev, r->prop_tiles, r->n_prop, st));
         HIP_TRY(hipEventRecord(b, st));
-        HIP_TRY(launch_propagate_deep(kind, prec, r->dev, 1, st));
-        HIP_TRY(launch_fold_max(r->dev, 1, st));
+        if (!fused) HIP_TRY(launch_fold_max(r->dev, 1, st));
         HIP_TRY(hipEventRecord(c, st));
         r->timed.push_back(smc_run::Timed{0, a, b});
-        r->timed.push_back(smc_run::Timed{1, b, c});
+        if (!fused) r->timed.push_back(smc_run::Timed{1, b, c});
     } else {
         HIP_TRY(launch_propagate(kind, prec, r->dev, r->prop_tiles, r->n_prop, st));
-        HIP_TRY(launch_propagate_deep(kind, prec, r->dev, 1, st));
-        HIP_TRY(launch_fold_max(r->dev, 1, st));
+        if (!fused) HIP_TRY(launch_fold_max(r->dev, 1, st));
     }
     r->expect_step = false;
     return SMC_OK;
@@ -255,14 +256,15 @@ smc_status do_resample(smc_run* r)
         hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
         if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
         HIP_TRY(hipEventRecord(a, st));
-        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, 1, st));
+        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, 1, r->host.fused == 0, st));
         HIP_TRY(hipEventRecord(b, st));
         HIP_TRY(launch_scan_anc(r->dev, r->red_tiles, r->n_red, st));
         HIP_TRY(hipEventRecord(c, st));
         r->timed.push_back(smc_run::Timed{2, a, b});
         r->timed.push_back(smc_run::Timed{3, b, c});
     } else {
-        HIP_TRY(launch_resample(r->dev, r->red_tiles, r->n_red, 1, st));
+        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, 1, r->host.fused == 0, st));
+        HIP_TRY(launch_scan_anc(r->dev, r->red_tiles, r->n_red, st));
     }
     r->expect_step = true;
     r->rounds_issued += 1;
@@ -470,10 +472,11 @@ static smc_status capture_run(smc_run* r, uint32_t rounds)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     for (uint32_t k = 0; k < rounds && e == hipSuccess; ++k) {
+        const bool fused = r->host.fused != 0;
         e = launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, cap);
-        if (e == hipSuccess) e = launch_propagate_deep(r->model->kind, r->model->precision, r->dev, 1, cap);
-        if (e == hipSuccess) e = launch_fold_max(r->dev, 1, cap);
-        if (e == hipSuccess) e = launch_resample(r->dev, r->red_tiles, r->n_red, 1, cap);
+        if (e == hipSuccess && !fused) e = launch_fold_max(r->dev, 1, cap);
+        if (e == hipSuccess) e = launch_reduce(r->dev, r->red_tiles, r->n_red, 1, !fused, cap);
+        if (e == hipSuccess) e = launch_scan_anc(r->dev, r->red_tiles, r->n_red, cap);
     }
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
@@ -493,7 +496,7 @@ smc_status smc_run_to_end(smc_run* r)
     if (!r) return fail(SMC_ERR_INVALID, "NULL run");
     if (r->known_status != SMC_OK) return r->known_status;
     const uint32_t known = lockstep_rounds(r->model);
-    if (known && r->rounds_issued == 0 && r->expect_step && !r->profiling) {
+    if (known && r->rounds_issued == 0 && r->expect_step && !r->profiling && (r->graph || r->resets > 0)) {
         if (!r->graph) {
             smc_status s = capture_run(r, known);
             if (s != SMC_OK) return s;
@@ -535,6 +538,7 @@ smc_status smc_reset(smc_run* r, uint64_t seed)
     r->expect_step = true;
     r->rounds_issued = 0;
     r->known_status = SMC_OK;
+    r->resets += 1;
     return SMC_OK;
 }
 
@@ -679,6 +683,7 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     h.n = (uint32_t)n;
     h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
     h.prop_tiles = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
+    h.fused = h.prop_tiles <= kMaxFusedPropTiles ? 1u : 0u;
     h.lw = const_cast<double*>(lw);
     h.anc = anc;
     h.ctl = (RunCtl*)arena.get(sizeof(RunCtl));
@@ -707,8 +712,9 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     if (e == hipSuccess) e = hipMemcpyAsync(tiles, th.data(), sizeof(TileRef) * th.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(ptiles, ph.data(), sizeof(TileRef) * ph.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_maxkey(dev, ptiles, h.prop_tiles, st);
-    if (e == hipSuccess) e = launch_fold_max(dev, 1, st);
-    if (e == hipSuccess) e = launch_resample(dev, tiles, h.red_tiles, 1, st);
+    if (e == hipSuccess && !h.fused) e = launch_fold_max(dev, 1, st);
+    if (e == hipSuccess) e = launch_reduce(dev, tiles, h.red_tiles, 1, !h.fused, st);
+    if (e == hipSuccess) e = launch_scan_anc(dev, tiles, h.red_tiles, st);
     if (e == hipSuccess) e = hipMemcpyAsync(logz_inc, &h.ctl->log_z, sizeof(double), hipMemcpyDeviceToDevice, st);
     RunCtl c{};
     if (e == hipSuccess) e = hipMemcpyAsync(&c, h.ctl, sizeof(RunCtl), hipMemcpyDeviceToHost, st);
@@ -738,6 +744,7 @@ struct smc_batch {
     TileRef* red_tiles = nullptr;
     uint32_t n_red = 0;
     std::vector<RunDev> runs_h;
+    bool any_unfused = false;
     std::vector<std::vector<TileRef>> group_tiles_h;
     std::vector<TileRef> red_tiles_h;
 };
@@ -753,6 +760,7 @@ smc_status rebuild_tables(smc_batch* b)
     b->runs_h.clear();
     b->group_tiles_h.clear();
     b->red_tiles_h.clear();
+    b->any_unfused = false;
     struct Key {
         int kind, precision;
     };
@@ -761,6 +769,7 @@ smc_status rebuild_tables(smc_batch* b)
         if (!r) continue;
         const uint32_t idx = (uint32_t)b->runs_h.size();
         b->runs_h.push_back(r->host);
+        if (!r->host.fused) b->any_unfused = true;
         size_t g = 0;
         for (; g < keys.size(); ++g)
             if (keys[g].kind == r->model->kind && keys[g].precision == r->model->precision) break;
@@ -840,9 +849,9 @@ smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
     for (int32_t k = 0; k < rounds; ++k) {
         for (const auto& g : b->groups) HIP_TRY(launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, st));
         const uint32_t n_runs = (uint32_t)b->runs_h.size();
-        for (const auto& g : b->groups) HIP_TRY(launch_propagate_deep(g.kind, g.precision, b->runs, n_runs, st));
-        HIP_TRY(launch_fold_max(b->runs, n_runs, st));
-        HIP_TRY(launch_resample(b->runs, b->red_tiles, b->n_red, n_runs, st));
+        if (b->any_unfused) HIP_TRY(launch_fold_max(b->runs, n_runs, st));
+        HIP_TRY(launch_reduce(b->runs, b->red_tiles, b->n_red, n_runs, b->any_unfused, st));
+        HIP_TRY(launch_scan_anc(b->runs, b->red_tiles, b->n_red, st));
     }
     for (smc_run* r : b->slots)
         if (r) r->rounds_issued += (uint32_t)rounds;

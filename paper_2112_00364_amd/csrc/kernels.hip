@@ -4,17 +4,22 @@
 // (run, tile) work-groups, so one launch serves any number of runs:
 //   k_propagate  Alg. 1 step 2: each lane takes one particle slot j, gathers
 //                its (block, state) from the ancestor chosen by the previous
-//                resampling (the duplication step of Sec. 3.3 done on read),
+//                resampling (the duplication step of Sec. 3.3, done on read),
 //                runs blocks until a checkpoint or b_stop and writes block,
-//                state and log-weight; work-group maxima feed the run's max.
-//   k_reduce     sum of exp(lw - M) (for log Z) and of the grid-quantised
-//                weights per tile; the last work-group of a run folds the
-//                partials in a fixed order, updates log Z (Sec. 3.3), decides
-//                termination and prepares the exclusive tile offsets.
-//   k_scan_anc   exact FP64 inclusive scan of the quantised weights inside the
-//                tile, offspring counts by integer comparison, and the
-//                ancestor indices of every output slot the tile owns
-//                (systematic resampling, Sec. 3.3).
+//                state and log-weight; each work-group stores its partial
+//                (max log-weight key, active count, NaN flag, block steps).
+//   k_reduce     folds the propagation partials of its run (M = max lw), then
+//                sums exp(lw - M) (for log Z) and the grid-quantised weights of
+//                its tile; tile 0 publishes M and the round's offset word.
+//   k_scan_anc   folds the tile sums of its run (total mass, tile offset),
+//                scans the quantised weights inside the tile exactly, turns
+//                cumulative mass into offspring counts by integer comparison
+//                and writes the ancestor of every output slot it owns
+//                (systematic resampling, Sec. 3.3); tile 0 updates log Z,
+//                decides termination and advances the round.
+// Runs above kMaxFusedPropTiles propagation tiles fold their partials in two
+// one-work-group kernels (k_fold_max, k_fold_sums) instead. No kernel uses
+// same-address atomics: partials are plain stores folded in a fixed order.
 // Memory is structure-of-arrays (Sec. 3.3): consecutive lanes touch
 // consecutive elements of each field.
 #include <type_traits>
@@ -47,13 +52,6 @@ __device__ inline int grid_bits(uint32_t n)
     return g < 32 ? g : 32;
 }
 
-// Grid-quantised weight of log-weight x against the maximum M.
-__device__ inline double quantised(double x, double M, double scale)
-{
-    const double e = fn::exp(x - M);
-    return __builtin_rint(e * scale);
-}
-
 // 64 x 64 -> 128-bit product.
 struct U128 {
     unsigned long long hi, lo;
@@ -65,9 +63,19 @@ __device__ inline U128 mul128(unsigned long long a, unsigned long long b)
 __device__ inline bool less128(U128 a, U128 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
 
 // Number of output slots j in [0, N) whose systematic position lies below
-// cumulative mass W (grid units): #{ j : (j 2^32 + U) Qtot < N W 2^32 }.
-__device__ inline uint32_t offspring_before(double W, double Qtot, uint32_t U, uint32_t N)
+// cumulative mass W (grid units): #{ j : (j 2^32 + U) Qtot < N W 2^32 }, i.e.
+// the number of integers j < y = N W / Qtot - U 2^-32. The FP64 estimate of y
+// is within 1e-8 of y, so away from integers its ceiling is exact; within
+// 2^-20 of an integer the count is settled by exact 128-bit comparisons.
+__device__ inline uint32_t offspring_before(double W, double Qtot, double rQ, uint32_t U, uint32_t N)
 {
+    const double y = (double)N * (W * rQ) - (double)U * 0x1p-32;
+    const double fl = __builtin_floor(y);
+    const double frac = y - fl;
+    if (frac > 0x1p-20 && frac < 1.0 - 0x1p-20) {
+        const double c = fl + 1.0;
+        return c <= 0.0 ? 0u : (c >= (double)N ? N : (uint32_t)c);
+    }
     const unsigned long long w = (unsigned long long)W;
     const unsigned long long qt = (unsigned long long)Qtot;
     const U128 nw = mul128((unsigned long long)N, w);  // < 2^78
@@ -76,8 +84,7 @@ __device__ inline uint32_t offspring_before(double W, double Qtot, uint32_t U, u
         const unsigned long long pos = ((unsigned long long)j << 32) | (unsigned long long)U;
         return less128(mul128(pos, qt), rhs);
     };
-    double y = (double)N * (W / Qtot) - (double)U * 0x1p-32;
-    double cf = __builtin_ceil(y);
+    const double cf = __builtin_ceil(y);
     uint32_t c = cf <= 0.0 ? 0u : (cf >= (double)N ? N : (uint32_t)cf);
     while (c > 0 && !below(c - 1)) c -= 1;
     while (c < N && below(c)) c += 1;
@@ -102,6 +109,52 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// Partial of a set of particles: max key, active count, NaN flag, block steps.
+struct Partial {
+    unsigned long long key;
+    uint32_t act, bad, steps;
+};
+
+__device__ inline Partial combine(Partial a, Partial b)
+{
+    return Partial{a.key > b.key ? a.key : b.key, a.act + b.act, a.bad | b.bad, a.steps + b.steps};
+}
+
+__device__ inline Partial wave_partial(Partial p)
+{
+    p.key = wave_max_u64(p.key);
+    p.act = wave_sum(p.act);
+    p.bad = wave_sum(p.bad) ? 1u : 0u;
+    p.steps = wave_sum(p.steps);
+    return p;
+}
+
+// Work-group reduction of a Partial (fixed order); every thread gets the result.
+template <int kThreads>
+__device__ inline Partial block_partial(Partial p)
+{
+    __shared__ Partial s_part[kThreads / 64];
+    p = wave_partial(p);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) s_part[wave] = p;
+    __syncthreads();
+    Partial r = s_part[0];
+    for (int w = 1; w < kThreads / 64; ++w) r = combine(r, s_part[w]);
+    return r;
+}
+
+// Fold a run's propagation partials (every thread of the work-group gets the result).
+template <int kThreads>
+__device__ inline Partial fold_prop_partials(const RunDev& R)
+{
+    Partial p{0ull, 0u, 0u, 0u};
+    for (uint32_t t = threadIdx.x; t < R.prop_tiles; t += kThreads) {
+        const uint32_t c = R.part_cnt[t];
+        p = combine(p, Partial{R.part_key[t], c & 0x7fffffffu, c >> 31, R.part_steps[t]});
+    }
+    return block_partial<kThreads>(p);
+}
+
 // ---------------------------------------------------------------------------
 // Propagation (Alg. 1 step 2) with gather-on-read of the previous resampling.
 // ---------------------------------------------------------------------------
@@ -116,12 +169,21 @@ __device__ inline void store_real(void* p, uint32_t i, double v)
     static_cast<Real*>(p)[i] = (Real)v;
 }
 
+// CRBD frame stacks: registers on the fast path, LDS for the rare deep particle.
+template <bool kDeep>
+struct CrbdStack {
+    using type = typename std::conditional<kDeep, LdsFrames<CrbdFrame>, RegFrames<CrbdFrame, kRegFrames>>::type;
+};
+
+// Bytes of one wavefront's LDS stack for the deep pass.
+constexpr int kDeepStackBytes = kMaxDepthCap * sizeof(CrbdFrame);
+
 // One particle slot j of round `round`: gather (block, state) from the
-// ancestor src, run blocks until a checkpoint or b_stop, store the results.
-// Returns false (storing nothing) when the hidden-lineage stack overflowed.
-template <int Kind, class Real, bool kFast>
+// ancestor, run blocks until a checkpoint or b_stop, store the results.
+// Returns false (storing nothing) when a register stack overflowed.
+template <int Kind, class Real, bool kDeep>
 __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t j, uint32_t round, uint8_t& blk,
-                                    double& lw, uint32_t& steps)
+                                    double& lw, uint32_t& steps, void* lds_stack)
 {
     const ParticleBuf& out = R.buf[round & 1u];
     const ParticleBuf& in = R.buf[(round & 1u) ^ 1u];
@@ -151,7 +213,9 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t
         }
         store_real<Real>(out.real[0], j, st.x);
     } else if constexpr (Kind == 2) {
-        using Stack = typename std::conditional<kFast, RegFrames<CrbdFrame, kRegFrames>, ArrayFrames<CrbdFrame>>::type;
+        using Stack = typename CrbdStack<kDeep>::type;
+        Stack stack;
+        if constexpr (kDeep) stack.base = static_cast<CrbdFrame*>(lds_stack);
         typename Crbd<Real>::State st{0.0, 0.0};
         if (round > 0) {
             st.lambda = load_real<Real>(in.real[0], src);
@@ -159,7 +223,7 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t
         }
         while (blk != kStop) {
             bool ck = false;
-            blk = Crbd<Real>::template sim<Stack>(m, round, blk, st, lw, s, ck, overflow);
+            blk = Crbd<Real>::template sim<Stack>(m, round, blk, st, lw, s, ck, overflow, stack);
             if (overflow) return false;
             steps += 1;
             if (ck) break;
@@ -167,8 +231,10 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t
         store_real<Real>(out.real[0], j, st.lambda);
         store_real<Real>(out.real[1], j, st.mu);
     } else {
-        using Stack =
-            typename std::conditional<kFast, RegFrames<ClaDSPending, kRegFrames>, ArrayFrames<ClaDSPending>>::type;
+        using Stack = ClaDSGlobalFrames;
+        const uint64_t levels = (uint64_t)kMaxDepthCap * R.n;
+        Stack stack{static_cast<double*>(R.side_stack), static_cast<double*>(R.side_stack) + levels,
+                    reinterpret_cast<uint8_t*>(static_cast<double*>(R.side_stack) + 2 * levels), (uint64_t)R.n, j};
         typename Clads<Real>::State st{0.0, 0.0, 0.0, 0.0};
         if (round > 0) {
             st.lambda = load_real<Real>(in.real[0], src);
@@ -180,7 +246,7 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t
                                          (uint64_t)R.n, src, j};
         while (blk != kStop) {
             bool ck = false;
-            blk = Clads<Real>::template sim<Stack>(m, round, blk, st, lw, s, ck, io, overflow);
+            blk = Clads<Real>::template sim<Stack>(m, round, blk, st, lw, s, ck, io, overflow, stack);
             if (overflow) return false;
             steps += 1;
             if (ck) break;
@@ -195,10 +261,10 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t
     return true;
 }
 
-// Fast pass over every particle: hidden-lineage stacks live in registers. A
-// particle whose stack would need more frames is appended to the run's
-// overflow list instead and recomputed by k_propagate_deep (its random stream
-// is counter-based, so the recomputation draws the same words).
+// Hidden-lineage stacks live in registers (kRegFrames frames). A particle that
+// needs more is recomputed, in the same work-group, one lane of its wavefront
+// at a time with a kMaxDepthCap-frame stack in LDS; its random stream is
+// counter-based, so the recomputation draws the same words.
 template <int Kind, class Real>
 __global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __restrict__ runs,
                                                              const TileRef* __restrict__ tiles)
@@ -210,189 +276,73 @@ __global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __rest
     const uint32_t round = ctl->round;
     const ModelDev& m = *R.model;
     const uint32_t j = tr.tile * kPropThreads + threadIdx.x;
-    bool counted = false;
+    const bool valid = j < R.n;
     uint8_t blk = kStop;
     double lw = 0.0;
     uint32_t steps = 0;
-    if (j < R.n) {
-        if (run_particle<Kind, Real, true>(R, m, j, round, blk, lw, steps)) {
-            counted = true;
-        } else {
-            const uint32_t slot = atomicAdd(&ctl->deep_count, 1u);
-            R.deep_list[slot] = j;
+    bool deep = false;
+    if (valid) deep = !run_particle<Kind, Real, false>(R, m, j, round, blk, lw, steps, nullptr);
+    if constexpr (Kind == 2) {
+        __shared__ __align__(16) unsigned char s_stack[kPropThreads / 64][kDeepStackBytes];
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        unsigned long long pending = __ballot(deep);
+        while (pending) {
+            const int leader = __ffsll((long long)pending) - 1;
+            if (lane == leader) run_particle<Kind, Real, true>(R, m, j, round, blk, lw, steps, s_stack[wave]);
+            pending &= pending - 1;
         }
     }
-
-    // work-group reduction: max key, bad flag, active count, block steps
-    unsigned long long key = 0;
-    uint32_t bad = 0, act = 0;
-    if (counted) {
-        if (lw != lw || lw == __builtin_huge_val()) bad = 1;
-        else key = order_key(lw);
-        act = blk != kStop ? 1u : 0u;
-    } else {
-        steps = 0;
+    Partial p{0ull, 0u, 0u, 0u};
+    if (valid) {
+        if (lw != lw || lw == __builtin_huge_val()) p.bad = 1;
+        else p.key = order_key(lw);
+        p.act = blk != kStop ? 1u : 0u;
+        p.steps = steps;
     }
-    key = wave_max_u64(key);
-    bad = wave_sum(bad);
-    act = wave_sum(act);
-    steps = wave_sum(steps);
-    __shared__ unsigned long long s_key[kPropThreads / 64];
-    __shared__ uint32_t s_bad[kPropThreads / 64], s_act[kPropThreads / 64], s_steps[kPropThreads / 64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        s_key[wave] = key;
-        s_bad[wave] = bad;
-        s_act[wave] = act;
-        s_steps[wave] = steps;
-    }
-    __syncthreads();
+    const Partial r = block_partial<kPropThreads>(p);
     if (threadIdx.x == 0) {
-        unsigned long long k = s_key[0];
-        uint32_t b = s_bad[0], a = s_act[0], st = s_steps[0];
-        for (int w = 1; w < kPropThreads / 64; ++w) {
-            k = s_key[w] > k ? s_key[w] : k;
-            b += s_bad[w];
-            a += s_act[w];
-            st += s_steps[w];
-        }
-        // per-tile partials, folded by k_fold_max (no same-address atomics)
-        R.part_key[tr.tile] = k;
-        R.part_cnt[tr.tile] = a | (b ? 0x80000000u : 0u);
-        R.part_steps[tr.tile] = st;
+        R.part_key[tr.tile] = r.key;
+        R.part_cnt[tr.tile] = r.act | (r.bad << 31);
+        R.part_steps[tr.tile] = r.steps;
     }
 }
 
-// Particles handed over by the fast pass, recomputed with a stack of
-// kMaxDepthCap frames. kDeepGroups work-groups per run stride over the run's
-// overflow list (usually a few dozen entries, often none).
-constexpr int kDeepGroups = 4;
-
-template <int Kind, class Real>
-__global__ __launch_bounds__(kPropThreads) void k_propagate_deep(const RunDev* __restrict__ runs)
-{
-    const RunDev& R = runs[blockIdx.x / kDeepGroups];
-    RunCtl* ctl = R.ctl;
-    if (ctl->status != 0 || R.model->kind != Kind || R.model->precision != (int)(8 * sizeof(Real))) return;
-    const uint32_t count = ctl->deep_count;
-    if (count == 0) return;  // uniform: k_fold_max ignores the deep partials then
-    const uint32_t round = ctl->round;
-    const uint32_t g = blockIdx.x % kDeepGroups;
-    unsigned long long key = 0;
-    uint32_t bad = 0, act = 0, steps_all = 0;
-    for (uint32_t i = g * kPropThreads + threadIdx.x; i < count; i += kDeepGroups * kPropThreads) {
-        const uint32_t j = R.deep_list[i];
-        uint8_t blk;
-        double lw;
-        uint32_t steps;
-        run_particle<Kind, Real, false>(R, *R.model, j, round, blk, lw, steps);
-        if (lw != lw || lw == __builtin_huge_val()) bad = 1;
-        else {
-            const unsigned long long kk = order_key(lw);
-            key = kk > key ? kk : key;
-        }
-        act += blk != kStop ? 1u : 0u;
-        steps_all += steps;
-    }
-    key = wave_max_u64(key);
-    bad = wave_sum(bad);
-    act = wave_sum(act);
-    steps_all = wave_sum(steps_all);
-    __shared__ unsigned long long s_key[kPropThreads / 64];
-    __shared__ uint32_t s_bad[kPropThreads / 64], s_act[kPropThreads / 64], s_steps[kPropThreads / 64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        s_key[wave] = key;
-        s_bad[wave] = bad;
-        s_act[wave] = act;
-        s_steps[wave] = steps_all;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long k = s_key[0];
-        uint32_t b = s_bad[0], a = s_act[0], st = s_steps[0];
-        for (int w = 1; w < kPropThreads / 64; ++w) {
-            k = s_key[w] > k ? s_key[w] : k;
-            b += s_bad[w];
-            a += s_act[w];
-            st += s_steps[w];
-        }
-        ctl->deep_key[g] = k;
-        ctl->deep_cnt[g] = a | (b ? 0x80000000u : 0u);
-        ctl->deep_steps[g] = st;
-    }
-}
-
-// One work-group per run folds the propagation partials: M (as a key), the
-// NaN flag, the number of active particles and the block steps of the round.
+// ---------------------------------------------------------------------------
+// Reduction: M, then per-tile sums of exp(lw - M) and grid units.
+// ---------------------------------------------------------------------------
 constexpr int kFoldThreads = 1024;
 
-__global__ __launch_bounds__(kFoldThreads) void k_fold_max(const RunDev* __restrict__ runs)
+// Publishes the round's fold of the propagation partials (one writer per run).
+__device__ inline void publish_fold(const RunDev& R, RunCtl* ctl, const Partial& f)
 {
-    const RunDev& R = runs[blockIdx.x];
-    RunCtl* ctl = R.ctl;
-    if (ctl->status != 0) return;
-    unsigned long long key = 0;
-    uint32_t bad = 0, act = 0, steps = 0;
-    for (uint32_t t = threadIdx.x; t < R.prop_tiles; t += kFoldThreads) {
-        const unsigned long long k = R.part_key[t];
-        const uint32_t c = R.part_cnt[t];
-        key = k > key ? k : key;
-        act += c & 0x7fffffffu;
-        bad |= c >> 31;
-        steps += R.part_steps[t];
-    }
-    if (ctl->deep_count > 0 && threadIdx.x < kDeepGroups) {
-        const unsigned long long k = ctl->deep_key[threadIdx.x];
-        const uint32_t c = ctl->deep_cnt[threadIdx.x];
-        key = k > key ? k : key;
-        act += c & 0x7fffffffu;
-        bad |= c >> 31;
-        steps += ctl->deep_steps[threadIdx.x];
-    }
-    key = wave_max_u64(key);
-    bad = wave_sum(bad);
-    act = wave_sum(act);
-    steps = wave_sum(steps);
-    __shared__ unsigned long long s_key[kFoldThreads / 64];
-    __shared__ uint32_t s_bad[kFoldThreads / 64], s_act[kFoldThreads / 64], s_steps[kFoldThreads / 64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        s_key[wave] = key;
-        s_bad[wave] = bad;
-        s_act[wave] = act;
-        s_steps[wave] = steps;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long k = 0;
-        uint32_t b = 0, a = 0;
-        unsigned long long st = 0;
-        for (int w = 0; w < kFoldThreads / 64; ++w) {
-            k = s_key[w] > k ? s_key[w] : k;
-            b += s_bad[w];
-            a += s_act[w];
-            st += s_steps[w];
-        }
-        ctl->maxkey = k;
-        ctl->bad = b ? 1u : 0u;
-        ctl->active = a;
-        ctl->block_steps += st;
-    }
+    ctl->maxkey = f.key;
+    ctl->bad = f.bad;
+    ctl->active = f.act;
+    ctl->block_steps += f.steps;
+    const uint32_t round = ctl->round;
+    ctl->u = philox10(0u, 0u, round, kTagResample, (uint32_t)R.seed, (uint32_t)(R.seed >> 32)).w0;
 }
 
-// ---------------------------------------------------------------------------
-// Reduction: per-tile sums, then the run's last work-group finalises.
-// ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict__ runs,
                                                          const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
     const RunDev& R = runs[tr.run];
-    const RunCtl* ctl = R.ctl;
-    if (ctl->status != 0 || ctl->bad != 0) return;
-    const double M = key_value(ctl->maxkey);
-    if (ctl->maxkey == 0 || M == -__builtin_huge_val()) return;
+    RunCtl* ctl = R.ctl;
+    if (ctl->status != 0) return;
+    unsigned long long key;
+    bool bad;
+    if (R.fused) {
+        const Partial f = fold_prop_partials<kRedThreads>(R);
+        if (tr.tile == 0 && threadIdx.x == 0) publish_fold(R, ctl, f);
+        key = f.key;
+        bad = f.bad != 0;
+    } else {
+        key = ctl->maxkey;
+        bad = ctl->bad != 0;
+    }
+    const double M = key_value(key);
+    if (bad || key == 0 || M == -__builtin_huge_val()) return;  // uniform over the work-group
     const double scale = (double)(1ull << grid_bits(R.n));
     double sq = 0.0, se = 0.0;
     const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
@@ -425,14 +375,37 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
     }
 }
 
-// One work-group per run: fold the tile sums in tile order, write each tile's
-// exclusive offset in grid units (exact in FP64), update log Z (Sec. 3.3),
-// decide termination and draw the round's resampling offset word.
+// log Z update, termination and the next round (one writer per run).
+__device__ inline void finish_round(const RunDev& R, RunCtl* ctl, bool bad, bool usable, double M, double S,
+                                    bool resampled)
+{
+    if (bad) {
+        ctl->status = -5;  // SMC_ERR_NAN
+    } else if (!usable) {
+        ctl->log_z = -__builtin_huge_val();
+        ctl->status = -6;  // SMC_DEGENERATE
+    } else {
+        ctl->log_z = ctl->log_z + ((M + fn::log(S)) - fn::log((double)R.n));
+        if (resampled) ctl->round = ctl->round + 1;
+        else ctl->status = 1;  // SMC_FINISHED
+    }
+}
+
+// Fold-kernel path (large runs): one work-group per run.
+__global__ __launch_bounds__(kFoldThreads) void k_fold_max(const RunDev* __restrict__ runs)
+{
+    const RunDev& R = runs[blockIdx.x];
+    RunCtl* ctl = R.ctl;
+    if (ctl->status != 0 || R.fused) return;
+    const Partial f = fold_prop_partials<kFoldThreads>(R);
+    if (threadIdx.x == 0) publish_fold(R, ctl, f);
+}
+
 __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __restrict__ runs)
 {
     const RunDev& R = runs[blockIdx.x];
     RunCtl* ctl = R.ctl;
-    if (ctl->status != 0) return;
+    if (ctl->status != 0 || R.fused) return;
     const bool bad = ctl->bad != 0;
     const double M = key_value(ctl->maxkey);
     const bool usable = !bad && ctl->maxkey != 0 && M != -__builtin_huge_val();
@@ -472,24 +445,9 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __rest
         }
     }
     if (threadIdx.x == 0) {
-        const uint32_t round = ctl->round;
-        if (bad) {
-            ctl->status = -5;  // SMC_ERR_NAN
-        } else if (!usable) {
-            ctl->log_z = -__builtin_huge_val();
-            ctl->status = -6;  // SMC_DEGENERATE
-        } else {
-            ctl->log_z = ctl->log_z + ((M + fn::log(e_all)) - fn::log((double)R.n));
-            if (ctl->active == 0) {
-                ctl->status = 1;  // SMC_FINISHED
-            } else {
-                ctl->m_cur = M;
-                ctl->qtot = q_all;
-                ctl->u = philox10(0u, 0u, round, kTagResample, (uint32_t)R.seed, (uint32_t)(R.seed >> 32)).w0;
-                ctl->round = round + 1;
-            }
-        }
-        ctl->deep_count = 0;
+        ctl->m_cur = M;
+        ctl->qtot = q_all;
+        finish_round(R, ctl, bad, usable, M, e_all, ctl->active != 0);
     }
 }
 
@@ -501,34 +459,79 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
 {
     const TileRef tr = tiles[blockIdx.x];
     const RunDev& R = runs[tr.run];
-    const RunCtl* ctl = R.ctl;
+    RunCtl* ctl = R.ctl;
     if (ctl->status != 0) return;
-    const double M = ctl->m_cur;
-    const double Qtot = ctl->qtot;
+    // Stable during this kernel (written by k_reduce / k_fold_* of this round).
+    // Only tile 0 writes the control block here, and nothing it writes is read
+    // by the other tiles except status, whose change (run finished or failed)
+    // also tells them to do nothing.
+    const unsigned long long key = ctl->maxkey;
+    const bool bad = ctl->bad != 0;
+    const bool resample = ctl->active != 0;
     const uint32_t U = ctl->u;
+    const double M = key_value(key);
+    const bool usable = !bad && key != 0 && M != -__builtin_huge_val();
     const uint32_t N = R.n;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ double s_wave[kRedThreads / 64];
+    __shared__ double s_wave2[kRedThreads / 64];
+    __shared__ double s_wave3[kRedThreads / 64];
+
+    double base = 0.0, Qtot = 0.0;
+    if (R.fused) {
+        // every work-group folds the run's tile sums: total mass and own offset
+        const uint32_t T = R.red_tiles;
+        double q_all = 0.0, q_before = 0.0, e_all = 0.0;
+        if (usable) {
+            for (uint32_t t = threadIdx.x; t < T; t += kRedThreads) {
+                const double q = R.part_q[t];
+                q_all += q;
+                if (t < tr.tile) q_before += q;
+                if (tr.tile == 0) e_all += R.part_e[t];
+            }
+        }
+        q_all = wave_sum(q_all);
+        q_before = wave_sum(q_before);
+        e_all = wave_sum(e_all);
+        if (lane == 0) {
+            s_wave[wave] = q_all;
+            s_wave2[wave] = q_before;
+            s_wave3[wave] = e_all;
+        }
+        __syncthreads();
+        double S = 0.0;
+        for (int w = 0; w < kRedThreads / 64; ++w) {
+            Qtot += s_wave[w];
+            base += s_wave2[w];
+            S += s_wave3[w];
+        }
+        if (tr.tile == 0 && threadIdx.x == 0) finish_round(R, ctl, bad, usable, M, S, resample);
+        __syncthreads();  // s_wave is reused below
+    } else {
+        Qtot = ctl->qtot;
+        base = usable ? R.prefix[tr.tile] : 0.0;
+    }
+    if (!usable || !resample) return;  // uniform over the work-group
+
     const double scale = (double)(1ull << grid_bits(N));
-    const double base = R.prefix[tr.tile];
+    const double rQ = 1.0 / Qtot;
     const uint32_t tile0 = tr.tile * kTileRed;
     const uint32_t first = tile0 + threadIdx.x * kRedItems;
-
     double q[kRedItems];
     double tsum = 0.0;
 #pragma unroll
     for (int k = 0; k < kRedItems; ++k) {
         const uint32_t i = first + k;
-        q[k] = i < N ? quantised(R.lw[i], M, scale) : 0.0;
+        q[k] = i < N ? __builtin_rint(fn::exp(R.lw[i] - M) * scale) : 0.0;
         tsum += q[k];
     }
-    // inclusive scan of thread sums across the work-group
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // inclusive scan of thread sums across the work-group (exact: integer-valued)
     double incl = tsum;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const double o = __shfl_up(incl, off, 64);
         if (lane >= off) incl += o;
     }
-    __shared__ double s_wave[kRedThreads / 64];
     __shared__ uint32_t s_c[kTileRed];
     __shared__ uint32_t s_o0;
     if (lane == 63) s_wave[wave] = incl;
@@ -539,26 +542,26 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
 #pragma unroll
     for (int k = 0; k < kRedItems; ++k) {
         W += q[k];
-        s_c[threadIdx.x * kRedItems + k] = offspring_before(W, Qtot, U, N);
+        s_c[threadIdx.x * kRedItems + k] = offspring_before(W, Qtot, rQ, U, N);
     }
-    if (threadIdx.x == 0) s_o0 = offspring_before(base, Qtot, U, N);
+    if (threadIdx.x == 0) s_o0 = offspring_before(base, Qtot, rQ, U, N);
     __syncthreads();
     const uint32_t count = (N - tile0) < (uint32_t)kTileRed ? (N - tile0) : (uint32_t)kTileRed;
     const uint32_t o0 = s_o0;
     const uint32_t o1 = s_c[count - 1];
-    for (uint32_t j = o0 + threadIdx.x; j < o1; j += kRedThreads) {
+    for (uint32_t jj = o0 + threadIdx.x; jj < o1; jj += kRedThreads) {
         uint32_t lo = 0, hi = count - 1;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (s_c[mid] > j) hi = mid;
+            if (s_c[mid] > jj) hi = mid;
             else lo = mid + 1;
         }
-        R.anc[j] = tile0 + lo;
+        R.anc[jj] = tile0 + lo;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Standalone pieces: max of a given weight vector, reads, self-tests.
+// Standalone pieces: max of a given weight vector, reads, self-tests, setup.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kPropThreads) void k_maxkey(const RunDev* __restrict__ runs,
                                                           const TileRef* __restrict__ tiles)
@@ -566,37 +569,22 @@ __global__ __launch_bounds__(kPropThreads) void k_maxkey(const RunDev* __restric
     const TileRef tr = tiles[blockIdx.x];
     const RunDev& R = runs[tr.run];
     const uint32_t i = tr.tile * kPropThreads + threadIdx.x;
-    unsigned long long key = 0;
-    uint32_t bad = 0;
+    Partial p{0ull, 0u, 0u, 0u};
     if (i < R.n) {
         const double x = R.lw[i];
-        if (x != x || x == __builtin_huge_val()) bad = 1;
-        else key = order_key(x);
+        if (x != x || x == __builtin_huge_val()) p.bad = 1;
+        else p.key = order_key(x);
+        p.act = 1;  // standalone resampling always resamples
     }
-    key = wave_max_u64(key);
-    bad = wave_sum(bad);
-    __shared__ unsigned long long s_key[kPropThreads / 64];
-    __shared__ uint32_t s_bad[kPropThreads / 64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) {
-        s_key[wave] = key;
-        s_bad[wave] = bad;
-    }
-    __syncthreads();
+    const Partial r = block_partial<kPropThreads>(p);
     if (threadIdx.x == 0) {
-        unsigned long long k = 0;
-        uint32_t b = 0;
-        for (int w = 0; w < kPropThreads / 64; ++w) {
-            k = s_key[w] > k ? s_key[w] : k;
-            b += s_bad[w];
-        }
-        R.part_key[tr.tile] = k;
-        R.part_cnt[tr.tile] = 1u | (b ? 0x80000000u : 0u);  // standalone resampling always resamples
+        R.part_key[tr.tile] = r.key;
+        R.part_cnt[tr.tile] = r.act | (r.bad << 31);
         R.part_steps[tr.tile] = 0;
     }
 }
 
-// Gathered copy of one array: dst[j] = src[anc[j]] (elements of `bytes` bytes).
+// Gathered copy of one array: dst[j] = src[anc[j]] for `levels` level-major rows.
 template <class T>
 __global__ void k_gather(const T* __restrict__ src, const uint32_t* __restrict__ anc, T* __restrict__ dst,
                          uint64_t n, uint64_t levels, uint64_t stride)
@@ -661,7 +649,6 @@ __global__ void k_reset(RunDev* run, uint64_t seed)
     c->status = 0;
     c->active = 0;
     c->bad = 0;
-    c->deep_count = 0;
 }
 
 // Derived model constants, computed with the pinned device functions so that
@@ -702,18 +689,6 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     return hipGetLastError();
 }
 
-hipError_t launch_propagate_deep(int kind, int precision, const RunDev* runs, uint32_t n_runs, hipStream_t st)
-{
-    // only the birth-death models have hidden-lineage stacks
-    if (n_runs == 0 || kind < 2) return hipSuccess;
-    dim3 g(n_runs * kDeepGroups), b(kPropThreads);
-    if (kind == 2 && precision == 32) hipLaunchKernelGGL((k_propagate_deep<2, float>), g, b, 0, st, runs);
-    else if (kind == 2) hipLaunchKernelGGL((k_propagate_deep<2, double>), g, b, 0, st, runs);
-    else if (precision == 32) hipLaunchKernelGGL((k_propagate_deep<3, float>), g, b, 0, st, runs);
-    else hipLaunchKernelGGL((k_propagate_deep<3, double>), g, b, 0, st, runs);
-    return hipGetLastError();
-}
-
 hipError_t launch_fold_max(const RunDev* runs, uint32_t n_runs, hipStream_t st)
 {
     if (n_runs == 0) return hipSuccess;
@@ -721,11 +696,12 @@ hipError_t launch_fold_max(const RunDev* runs, uint32_t n_runs, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs, hipStream_t st)
+hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs,
+                         bool any_unfused, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce, dim3(n_tiles), dim3(kRedThreads), 0, st, runs, tiles);
-    hipLaunchKernelGGL(k_fold_sums, dim3(n_runs), dim3(kFoldThreads), 0, st, runs);
+    if (any_unfused) hipLaunchKernelGGL(k_fold_sums, dim3(n_runs), dim3(kFoldThreads), 0, st, runs);
     return hipGetLastError();
 }
 
@@ -734,13 +710,6 @@ hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_
     if (n_tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_scan_anc, dim3(n_tiles), dim3(kRedThreads), 0, st, runs, tiles);
     return hipGetLastError();
-}
-
-hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs, hipStream_t st)
-{
-    hipError_t e = launch_reduce(runs, tiles, n_tiles, n_runs, st);
-    if (e != hipSuccess) return e;
-    return launch_scan_anc(runs, tiles, n_tiles, st);
 }
 
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)

@@ -9,10 +9,9 @@ namespace pcfg {
 
 hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const TileRef* tiles, uint32_t n_tiles,
                             hipStream_t st);
-hipError_t launch_propagate_deep(int kind, int precision, const RunDev* runs, uint32_t n_runs, hipStream_t st);
 hipError_t launch_fold_max(const RunDev* runs, uint32_t n_runs, hipStream_t st);
-hipError_t launch_resample(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs, hipStream_t st);
-hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs, hipStream_t st);
+hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs,
+                         bool any_unfused, hipStream_t st);
 hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
 hipError_t launch_gather(int elem_bytes, const void* src, const uint32_t* anc, void* dst, uint64_t n,

@@ -91,8 +91,8 @@ enum Hidden : int { kDetected = 0, kUndetected = 1, kOverflow = 2 };
 
 // Depth-first frame stacks. RegFrames keeps the K innermost frames in
 // registers (every index is a compile-time constant, so no scratch memory is
-// needed) and reports full() when a K+1-th frame is asked for; ArrayFrames is
-// the unbounded-in-practice variant (kMaxDepthCap frames, placed in scratch).
+// needed) and reports full() when a K+1-th frame is asked for; LdsFrames
+// holds all kMaxDepthCap frames in LDS.
 template <class Frame, int K>
 struct RegFrames {
     Frame f[K];
@@ -114,13 +114,15 @@ struct RegFrames {
     }
 };
 
+// LdsFrames holds up to kMaxDepthCap frames in a caller-provided LDS region
+// (one region per wavefront; used for one lane at a time).
 template <class Frame>
-struct ArrayFrames {
-    Frame f[kMaxDepthCap];
+struct LdsFrames {
+    Frame* base;
     int depth = 0;
     __device__ inline bool full() const { return false; }
-    __device__ inline Frame& top() { return f[depth - 1]; }
-    __device__ inline void push(const Frame& x) { f[depth++] = x; }
+    __device__ inline Frame& top() { return base[depth - 1]; }
+    __device__ inline void push(const Frame& x) { base[depth++] = x; }
     __device__ inline void pop() { depth -= 1; }
 };
 
@@ -142,9 +144,9 @@ struct CrbdSim {
     // the stack ran out of registers before any budget did (the caller then
     // recomputes the particle with a deeper stack).
     template <class Stack>
-    __device__ inline int undetected(Stream& s, double t0)
+    __device__ inline int undetected(Stream& s, double t0, Stack& stack)
     {
-        Stack stack;
+        stack.depth = 0;
         double enter_at = t0;
         bool entering = true;
         while (true) {
@@ -186,7 +188,7 @@ struct Crbd {
     // Stack: frame stack for hidden lineages; overflow is set when it ran out.
     template <class Stack>
     __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
-                                         Stream& s, bool& ckpt, bool& overflow)
+                                         Stream& s, bool& ckpt, bool& overflow, Stack& stack)
     {
         ckpt = true;
         if (b == 0) {
@@ -215,7 +217,7 @@ struct Crbd {
                 }
                 sim.events += 1;
                 const double t = draw_uniform(s, tc, tp);
-                const int h = sim.template undetected<Stack>(s, t);
+                const int h = sim.template undetected<Stack>(s, t, stack);
                 if (h == kOverflow) {
                     overflow = true;
                     return b;
@@ -242,6 +244,34 @@ struct ClaDSPending {
     int depth;
 };
 
+// ClaDS pending side lineages in device memory: level k of particle slot j at
+// k * stride + j (start time and rate in FP64, depth in a byte). Side-lineage
+// recursion under ClaDS is routinely deep, so every lane keeps a full
+// kMaxDepthCap-level stack here and no lane waits for another.
+struct ClaDSGlobalFrames {
+    double* start;
+    double* rate;
+    uint8_t* dep;
+    uint64_t stride;
+    uint32_t j;
+    int depth = 0;
+    __device__ inline bool full() const { return false; }
+    __device__ inline ClaDSPending top() const
+    {
+        const uint64_t at = (uint64_t)(depth - 1) * stride + j;
+        return ClaDSPending{start[at], rate[at], (int)dep[at]};
+    }
+    __device__ inline void push(const ClaDSPending& x)
+    {
+        const uint64_t at = (uint64_t)depth * stride + j;
+        start[at] = x.start;
+        rate[at] = x.rate;
+        dep[at] = (uint8_t)x.depth;
+        depth += 1;
+    }
+    __device__ inline void pop() { depth -= 1; }
+};
+
 struct ClaDSSide {
     double eps, log_alpha, sigma, rho;
     int events, max_events, max_depth;
@@ -253,9 +283,9 @@ struct ClaDSSide {
     // Depth-first: the second daughter waits on a stack while the first one's
     // subtree is simulated. Returns kUndetected, kDetected or kOverflow.
     template <class Stack>
-    __device__ inline int undetected(Stream& s, double t0, double r0)
+    __device__ inline int undetected(Stream& s, double t0, double r0, Stack& stack)
     {
-        Stack stack;
+        stack.depth = 0;
         double start = t0, rate = r0;
         int depth = 1;
         while (true) {
@@ -308,7 +338,7 @@ struct Clads {
     };
     template <class Stack>
     __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
-                                         Stream& s, bool& ckpt, const StackIO& io, bool& overflow)
+                                         Stream& s, bool& ckpt, const StackIO& io, bool& overflow, Stack& stack)
     {
         ckpt = true;
         if (b == 0) {
@@ -351,7 +381,7 @@ struct Clads {
             t = t - w;
             const double cont = lambda * draw_lognormal(s, log_alpha, st.sigma);
             const double sider = lambda * draw_lognormal(s, log_alpha, st.sigma);
-            const int h = side.template undetected<Stack>(s, t, sider);
+            const int h = side.template undetected<Stack>(s, t, sider, stack);
             if (h == kOverflow) {
                 overflow = true;
                 return b;

@@ -13,7 +13,7 @@ All SMC work runs in libpcfgsmc.so; this module is host-side scheduling only.
 from __future__ import annotations
 
 import collections
-import math
+import sys
 import time
 
 import numpy as np
@@ -23,11 +23,14 @@ from . import smc
 
 
 def footprint_bytes(kind: str, n: int, precision: int, stack_depth: int = 0) -> int:
-    """Device bytes of one run: double-buffered block + state (+ ClaDS stack),
-    log-weights, ancestors, deep list, tile partials."""
+    """Device bytes of one run: double-buffered block + state (+ ClaDS rate
+    stack), log-weights, ancestors, tile partials (+ ClaDS side-lineage stacks:
+    32 levels of 17 bytes per particle)."""
     real = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4}[kind]
     rb = 4 if precision == 32 else 8
-    per = 2 * (1 + real * rb + (stack_depth * rb if kind == "clads" else 0)) + 8 + 4 + 4
+    per = 2 * (1 + real * rb + (stack_depth * rb if kind == "clads" else 0)) + 8 + 4
+    if kind == "clads":
+        per += 32 * 17
     tiles = (n + 255) // 256
     return n * per + tiles * 16 + (n + 1023) // 1024 * 24 + 512
 
@@ -68,12 +71,18 @@ def rescale_arrivals(reqs, rate_per_s: float, seed: int):
     return reqs
 
 
-def serve_one_at_a_time(ctx: smc.Context, reqs, honour_arrivals=True):
+def _progress(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def serve_one_at_a_time(ctx: smc.Context, reqs, honour_arrivals=True, log_every=100):
     """FIFO, one plain run at a time."""
     import torch
     out = []
     t0 = time.perf_counter()
-    for r in reqs:
+    for k, r in enumerate(reqs):
+        if log_every and k % log_every == 0:
+            _progress(f"one-at-a-time: request {k}/{len(reqs)} at {time.perf_counter() - t0:.1f} s")
         now = time.perf_counter() - t0
         if honour_arrivals and r["arrival"] > now:
             time.sleep(r["arrival"] - now)
@@ -93,7 +102,7 @@ def serve_one_at_a_time(ctx: smc.Context, reqs, honour_arrivals=True):
 
 
 def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: int = 8,
-                  max_live: int = 256, honour_arrivals=True):
+                  max_live: int = 256, honour_arrivals=True, log_every=100):
     """Continuous batching: admit while memory and slots allow, tick, retire."""
     pending = collections.deque(sorted(reqs, key=lambda r: r["arrival"]))
     batch = smc.Batch(ctx)
@@ -128,6 +137,8 @@ def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: i
                 batch.retire(slot)
                 model.close()
                 used -= r["bytes"]
+                if log_every and len(out) % log_every == 0:
+                    _progress(f"batched: {len(out)}/{len(reqs)} done, {len(live)} live at {now:.1f} s")
     batch.close()
     return out, time.perf_counter() - t0
 

@@ -430,3 +430,11 @@ def test_clads_deep_side_lineages_match(smc, oracle, ctx):
     run_lockstep(smc, oracle, ctx, I.clads_spec(tree, precision=64, fixed_l0=8.0, fixed_eps=0.95, fixed_alpha=1.0,
                                                 fixed_sigma=0.0), 2048, 3)
     run_lockstep(smc, oracle, ctx, I.clads_spec(tree, precision=32, fixed_l0=6.0, fixed_eps=0.9), 2048, 4)
+
+
+def test_large_run_fold_kernel_path_matches(smc, oracle, ctx):
+    """Above 2^20 particles the propagation partials are folded by separate
+    one-work-group kernels; ragged size, round-by-round parity."""
+    y = I.lgssm_data(6, 31)
+    say("lgssm N=2^20+4097")
+    run_lockstep(smc, oracle, ctx, I.lgssm_spec(y, 32), (1 << 20) + 4097, 12, check_every=2)
