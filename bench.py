@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-run batched ClaDS leg")
     ap.add_argument("--serving-requests", type=int, default=2000, help="0 skips the serving leg")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -157,6 +159,14 @@ def main():
 
     from paper_2112_00364_amd import inputs as I
     from paper_2112_00364_amd import smc
+
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     tree = I.yule_tree(TIPS, TREE_SEED)
     spec = I.crbd_spec(tree, precision=32)

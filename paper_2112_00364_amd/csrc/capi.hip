@@ -166,7 +166,6 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     r->seed = seed;
     r->arena.ctx = ctx;
     RunDev& h = r->host;
-    h.seed = seed;
     h.n = (uint32_t)n;
     h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
     h.model = m->dev;
@@ -212,8 +211,8 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     for (uint32_t t = 0; t < r->n_prop; ++t) r->prop_tiles_h[t] = TileRef{0, t};
     for (uint32_t t = 0; t < r->n_red; ++t) r->red_tiles_h[t] = TileRef{0, t};
     hipStream_t st = ctx->stream;
-    HIP_TRY(hipMemsetAsync(h.ctl, 0, sizeof(RunCtl), st));
     HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_reset(r->dev, seed, st));  // control block: round 0, log Z 0, the seed
     HIP_TRY(hipMemcpyAsync(r->prop_tiles, r->prop_tiles_h.data(), sizeof(TileRef) * r->n_prop,
                            hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(r->red_tiles, r->red_tiles_h.data(), sizeof(TileRef) * r->n_red,
@@ -233,14 +232,14 @@ smc_status do_step(smc_run* r)
         hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
         if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
         HIP_TRY(hipEventRecord(a, st));
-        HIP_TRY(launch_propagate(kind, prec, r->dev, r->prop_tiles, r->n_prop, st));
+        HIP_TRY(launch_propagate_one(kind, prec, r->host, st));
         HIP_TRY(hipEventRecord(b, st));
         if (!fused) HIP_TRY(launch_fold_max(r->dev, 1, st));
         HIP_TRY(hipEventRecord(c, st));
         r->timed.push_back(smc_run::Timed{0, a, b});
         if (!fused) r->timed.push_back(smc_run::Timed{1, b, c});
     } else {
-        HIP_TRY(launch_propagate(kind, prec, r->dev, r->prop_tiles, r->n_prop, st));
+        HIP_TRY(launch_propagate_one(kind, prec, r->host, st));
         if (!fused) HIP_TRY(launch_fold_max(r->dev, 1, st));
     }
     r->expect_step = false;
@@ -256,15 +255,14 @@ smc_status do_resample(smc_run* r)
         hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
         if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
         HIP_TRY(hipEventRecord(a, st));
-        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, 1, r->host.fused == 0, st));
+        HIP_TRY(launch_resample_one(r->host, r->dev, st, 1));
         HIP_TRY(hipEventRecord(b, st));
-        HIP_TRY(launch_scan_anc(r->dev, r->red_tiles, r->n_red, st));
+        HIP_TRY(launch_resample_one(r->host, r->dev, st, 2));
         HIP_TRY(hipEventRecord(c, st));
         r->timed.push_back(smc_run::Timed{2, a, b});
         r->timed.push_back(smc_run::Timed{3, b, c});
     } else {
-        HIP_TRY(launch_reduce(r->dev, r->red_tiles, r->n_red, 1, r->host.fused == 0, st));
-        HIP_TRY(launch_scan_anc(r->dev, r->red_tiles, r->n_red, st));
+        HIP_TRY(launch_resample_one(r->host, r->dev, st, 3));
     }
     r->expect_step = true;
     r->rounds_issued += 1;
@@ -473,10 +471,9 @@ static smc_status capture_run(smc_run* r, uint32_t rounds)
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     for (uint32_t k = 0; k < rounds && e == hipSuccess; ++k) {
         const bool fused = r->host.fused != 0;
-        e = launch_propagate(r->model->kind, r->model->precision, r->dev, r->prop_tiles, r->n_prop, cap);
+        e = launch_propagate_one(r->model->kind, r->model->precision, r->host, cap);
         if (e == hipSuccess && !fused) e = launch_fold_max(r->dev, 1, cap);
-        if (e == hipSuccess) e = launch_reduce(r->dev, r->red_tiles, r->n_red, 1, !fused, cap);
-        if (e == hipSuccess) e = launch_scan_anc(r->dev, r->red_tiles, r->n_red, cap);
+        if (e == hipSuccess) e = launch_resample_one(r->host, r->dev, cap, 3);
     }
     hipError_t e2 = hipStreamEndCapture(cap, &g);
     if (e == hipSuccess) e = e2;
@@ -533,7 +530,6 @@ smc_status smc_reset(smc_run* r, uint64_t seed)
 {
     if (!r) return fail(SMC_ERR_INVALID, "NULL run");
     HIP_TRY(launch_reset(r->dev, seed, r->ctx->stream));
-    r->host.seed = seed;
     r->seed = seed;
     r->expect_step = true;
     r->rounds_issued = 0;
@@ -679,7 +675,6 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     DeviceArena arena;
     arena.ctx = ctx;
     RunDev h{};
-    h.seed = seed;
     h.n = (uint32_t)n;
     h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
     h.prop_tiles = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
@@ -706,6 +701,7 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     for (uint32_t t = 0; t < h.prop_tiles; ++t) ph[t] = TileRef{0, t};
     RunCtl c0{};
     c0.round = round;
+    c0.seed = seed;
     hipStream_t st = ctx->stream;
     hipError_t e = hipMemcpyAsync(h.ctl, &c0, sizeof(RunCtl), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(dev, &h, sizeof(RunDev), hipMemcpyHostToDevice, st);

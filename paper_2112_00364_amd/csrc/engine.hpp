@@ -18,7 +18,9 @@ struct alignas(64) RunCtl {
     int32_t status;                  // SMC_OK / FINISHED / ERR_NAN / DEGENERATE
     uint32_t active;                 // particles not at b_stop after this round's propagation
     uint32_t bad;                    // a NaN or +inf log-weight was produced
-    uint32_t pad[5];
+    uint32_t pad0;
+    unsigned long long seed;         // Philox key of the run (set by init / reset)
+    uint32_t pad[2];
 };
 
 // One particle buffer: block index, real fields (storage precision), int
@@ -31,7 +33,6 @@ struct ParticleBuf {
 };
 
 struct RunDev {
-    uint64_t seed;
     uint32_t n;
     uint32_t red_tiles;            // reduction / scan tiles of kTileRed particles
     uint32_t prop_tiles;           // propagation tiles of kPropThreads particles

@@ -46,8 +46,7 @@ __device__ inline double key_value(unsigned long long k)
 
 __device__ inline int grid_bits(uint32_t n)
 {
-    int cl = 0;
-    while ((1u << cl) < n) cl += 1;  // n <= 2^24
+    const int cl = n <= 1 ? 0 : 32 - __builtin_clz(n - 1);  // ceil(log2 n), n <= 2^24
     const int g = 53 - cl;
     return g < 32 ? g : 32;
 }
@@ -109,6 +108,36 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
+// Key stored for a tile that produced a NaN or +inf log-weight: above every
+// order_key of a non-NaN double, so a max over tile keys flags the round.
+constexpr unsigned long long kBadKey = ~0ull;
+
+// Max over a run's propagation tile keys (every thread gets the result). All
+// of a thread's loads are issued before any is used (at most
+// kMaxFusedPropTiles / kThreads of them), so the fold costs one memory latency.
+template <int kThreads>
+__device__ inline unsigned long long fold_prop_keys(const RunDev& R)
+{
+    constexpr int kPer = (int)(kMaxFusedPropTiles / kThreads);
+    unsigned long long v[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const uint32_t t = threadIdx.x + (uint32_t)i * kThreads;
+        v[i] = t < R.prop_tiles ? R.part_key[t] : 0ull;
+    }
+    unsigned long long key = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) key = v[i] > key ? v[i] : key;
+    key = wave_max_u64(key);
+    __shared__ unsigned long long s_key[kThreads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) s_key[wave] = key;
+    __syncthreads();
+    unsigned long long r = 0;
+    for (int w = 0; w < kThreads / 64; ++w) r = s_key[w] > r ? s_key[w] : r;
+    return r;
+}
+
 // Partial of a set of particles: max key, active count, NaN flag, block steps.
 struct Partial {
     unsigned long long key;
@@ -143,14 +172,49 @@ __device__ inline Partial block_partial(Partial p)
     return r;
 }
 
-// Fold a run's propagation partials (every thread of the work-group gets the result).
+// Work-group partial with no closing barrier: each wavefront leaves its
+// partial in LDS and counts itself in; the last to arrive combines the
+// partials in wavefront order and writes the tile's record. Wavefronts that
+// finish early exit at once and free their slots for the next work-group.
+// *arrived must be zero before any wavefront gets here.
+template <int kThreads>
+__device__ inline void publish_tile_partial(const RunDev& R, uint32_t tile, Partial p, uint32_t* arrived)
+{
+    __shared__ Partial s_part[kThreads / 64];
+    p = wave_partial(p);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane != 0) return;
+    s_part[wave] = p;
+    __threadfence_block();
+    if (atomicAdd(arrived, 1u) != (uint32_t)(kThreads / 64 - 1)) return;
+    __threadfence_block();
+    Partial r = s_part[0];
+    for (int w = 1; w < kThreads / 64; ++w) r = combine(r, s_part[w]);
+    R.part_key[tile] = r.bad ? kBadKey : r.key;
+    R.part_cnt[tile] = r.act | (r.bad << 31);
+    R.part_steps[tile] = r.steps;
+}
+
+// Fold a run's propagation partials (every thread of the work-group gets the
+// result); loads are issued in batches of kBatch independent requests.
 template <int kThreads>
 __device__ inline Partial fold_prop_partials(const RunDev& R)
 {
+    constexpr int kBatch = 8;
     Partial p{0ull, 0u, 0u, 0u};
-    for (uint32_t t = threadIdx.x; t < R.prop_tiles; t += kThreads) {
-        const uint32_t c = R.part_cnt[t];
-        p = combine(p, Partial{R.part_key[t], c & 0x7fffffffu, c >> 31, R.part_steps[t]});
+    for (uint32_t base = threadIdx.x; base < R.prop_tiles; base += kBatch * kThreads) {
+        unsigned long long kv[kBatch];
+        uint32_t cv[kBatch], sv[kBatch];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const uint32_t t = base + (uint32_t)i * kThreads;
+            const bool in = t < R.prop_tiles;
+            kv[i] = in ? R.part_key[t] : 0ull;
+            cv[i] = in ? R.part_cnt[t] : 0u;
+            sv[i] = in ? R.part_steps[t] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) p = combine(p, Partial{kv[i], cv[i] & 0x7fffffffu, cv[i] >> 31, sv[i]});
     }
     return block_partial<kThreads>(p);
 }
@@ -182,17 +246,17 @@ constexpr int kDeepStackBytes = kMaxDepthCap * sizeof(CrbdFrame);
 // ancestor, run blocks until a checkpoint or b_stop, store the results.
 // Returns false (storing nothing) when a register stack overflowed.
 template <int Kind, class Real, bool kDeep>
-__device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t j, uint32_t round, uint8_t& blk,
-                                    double& lw, uint32_t& steps, void* lds_stack)
+__device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint64_t seed, uint32_t j, uint32_t round,
+                                    uint32_t ancestor, uint8_t& blk, double& lw, uint32_t& steps, void* lds_stack)
 {
     const ParticleBuf& out = R.buf[round & 1u];
     const ParticleBuf& in = R.buf[(round & 1u) ^ 1u];
-    const uint32_t src = round > 0 ? R.anc[j] : j;
+    const uint32_t src = round > 0 ? ancestor : j;
     blk = round > 0 ? in.blk[src] : 0;
     lw = 0.0;
     steps = 0;
     Stream s;
-    s.start(R.seed, j, round, kTagPropagate);
+    s.start(seed, j, round, kTagPropagate);
     bool overflow = false;
     if constexpr (Kind == 0) {
         Geometric::State st{round > 0 ? in.ints[0][src] : 0};
@@ -266,29 +330,35 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint32_t
 // at a time with a kMaxDepthCap-frame stack in LDS; its random stream is
 // counter-based, so the recomputation draws the same words.
 template <int Kind, class Real>
-__global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __restrict__ runs,
-                                                             const TileRef* __restrict__ tiles)
+__device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
 {
-    const TileRef tr = tiles[blockIdx.x];
-    const RunDev& R = runs[tr.run];
-    RunCtl* ctl = R.ctl;
-    if (ctl->status != 0) return;  // uniform over the work-group
-    const uint32_t round = ctl->round;
-    const ModelDev& m = *R.model;
-    const uint32_t j = tr.tile * kPropThreads + threadIdx.x;
+    const uint32_t j = tile * kPropThreads + threadIdx.x;
     const bool valid = j < R.n;
+    // The ancestor index is loaded before the control block is consumed, so
+    // the two loads overlap (at round 0 the value is not used).
+    RunCtl* ctl = R.ctl;
+    const int32_t status = ctl->status;
+    const uint32_t round = ctl->round;
+    const uint64_t seed = ctl->seed;
+    const uint32_t ancestor = valid ? R.anc[j] : 0u;
+    if (status != 0) return;  // uniform over the work-group
+    __shared__ uint32_t s_arrived;
+    if (threadIdx.x == 0) s_arrived = 0;
+    __syncthreads();
+    const ModelDev& m = *R.model;
     uint8_t blk = kStop;
     double lw = 0.0;
     uint32_t steps = 0;
     bool deep = false;
-    if (valid) deep = !run_particle<Kind, Real, false>(R, m, j, round, blk, lw, steps, nullptr);
+    if (valid) deep = !run_particle<Kind, Real, false>(R, m, seed, j, round, ancestor, blk, lw, steps, nullptr);
     if constexpr (Kind == 2) {
         __shared__ __align__(16) unsigned char s_stack[kPropThreads / 64][kDeepStackBytes];
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         unsigned long long pending = __ballot(deep);
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
-            if (lane == leader) run_particle<Kind, Real, true>(R, m, j, round, blk, lw, steps, s_stack[wave]);
+            if (lane == leader)
+                run_particle<Kind, Real, true>(R, m, seed, j, round, ancestor, blk, lw, steps, s_stack[wave]);
             pending &= pending - 1;
         }
     }
@@ -299,12 +369,23 @@ __global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __rest
         p.act = blk != kStop ? 1u : 0u;
         p.steps = steps;
     }
-    const Partial r = block_partial<kPropThreads>(p);
-    if (threadIdx.x == 0) {
-        R.part_key[tr.tile] = r.key;
-        R.part_cnt[tr.tile] = r.act | (r.bad << 31);
-        R.part_steps[tr.tile] = r.steps;
-    }
+    publish_tile_partial<kPropThreads>(R, tile, p, &s_arrived);
+}
+
+// Entry points: one run (its record is a kernel argument, tile = work-group)
+// or a batch (work-group -> (run, tile) table).
+template <int Kind, class Real>
+__global__ __launch_bounds__(kPropThreads) void k_propagate_one(const RunDev R)
+{
+    propagate_body<Kind, Real>(R, blockIdx.x);
+}
+
+template <int Kind, class Real>
+__global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __restrict__ runs,
+                                                             const TileRef* __restrict__ tiles)
+{
+    const TileRef tr = tiles[blockIdx.x];
+    propagate_body<Kind, Real>(runs[tr.run], tr.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -320,37 +401,43 @@ __device__ inline void publish_fold(const RunDev& R, RunCtl* ctl, const Partial&
     ctl->active = f.act;
     ctl->block_steps += f.steps;
     const uint32_t round = ctl->round;
-    ctl->u = philox10(0u, 0u, round, kTagResample, (uint32_t)R.seed, (uint32_t)(R.seed >> 32)).w0;
+    const uint64_t seed = ctl->seed;
+    ctl->u = philox10(0u, 0u, round, kTagResample, (uint32_t)seed, (uint32_t)(seed >> 32)).w0;
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict__ runs,
-                                                         const TileRef* __restrict__ tiles)
+__device__ __forceinline__ void reduce_body(const RunDev& R, const TileRef tr)
 {
-    const TileRef tr = tiles[blockIdx.x];
-    const RunDev& R = runs[tr.run];
+    // The status, the tile's log-weights and the propagation partials are all
+    // requested before any of them is used, so their latencies overlap.
     RunCtl* ctl = R.ctl;
-    if (ctl->status != 0) return;
-    unsigned long long key;
-    bool bad;
-    if (R.fused) {
-        const Partial f = fold_prop_partials<kRedThreads>(R);
-        if (tr.tile == 0 && threadIdx.x == 0) publish_fold(R, ctl, f);
-        key = f.key;
-        bad = f.bad != 0;
-    } else {
-        key = ctl->maxkey;
-        bad = ctl->bad != 0;
-    }
-    const double M = key_value(key);
-    if (bad || key == 0 || M == -__builtin_huge_val()) return;  // uniform over the work-group
-    const double scale = (double)(1ull << grid_bits(R.n));
-    double sq = 0.0, se = 0.0;
+    const int32_t status = ctl->status;
+    double x[kRedItems];
     const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
 #pragma unroll
+    for (int k = 0; k < kRedItems; ++k) x[k] = base + k < R.n ? R.lw[base + k] : 0.0;
+    unsigned long long key = 0;
+    Partial f{0ull, 0u, 0u, 0u};
+    if (R.fused) {
+        if (tr.tile == 0) f = fold_prop_partials<kRedThreads>(R);
+        else key = fold_prop_keys<kRedThreads>(R);
+    }
+    if (status != 0) return;  // uniform over the work-group
+    if (R.fused) {
+        if (tr.tile == 0) {
+            if (threadIdx.x == 0) publish_fold(R, ctl, f);
+            key = f.bad ? kBadKey : f.key;
+        }
+    } else {
+        key = ctl->bad ? kBadKey : ctl->maxkey;
+    }
+    const double M = key_value(key);
+    if (key == kBadKey || key == 0 || M == -__builtin_huge_val()) return;  // uniform over the work-group
+    const double scale = (double)(1ull << grid_bits(R.n));
+    double sq = 0.0, se = 0.0;
+#pragma unroll
     for (int k = 0; k < kRedItems; ++k) {
-        const uint32_t i = base + k;
-        if (i < R.n) {
-            const double e = fn::exp(R.lw[i] - M);
+        if (base + k < R.n) {
+            const double e = fn::exp(x[k] - M);
             se += e;
             sq += __builtin_rint(e * scale);
         }
@@ -373,6 +460,18 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
         R.part_q[tr.tile] = q;
         R.part_e[tr.tile] = e;
     }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_one(const RunDev R)
+{
+    reduce_body(R, TileRef{0u, blockIdx.x});
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict__ runs,
+                                                         const TileRef* __restrict__ tiles)
+{
+    const TileRef tr = tiles[blockIdx.x];
+    reduce_body(runs[tr.run], tr);
 }
 
 // log Z update, termination and the next round (one writer per run).
@@ -454,41 +553,64 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __rest
 // ---------------------------------------------------------------------------
 // Exact scan + systematic ancestors for the output slots owned by each tile.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restrict__ runs,
-                                                           const TileRef* __restrict__ tiles)
+__device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
 {
-    const TileRef tr = tiles[blockIdx.x];
-    const RunDev& R = runs[tr.run];
-    RunCtl* ctl = R.ctl;
-    if (ctl->status != 0) return;
     // Stable during this kernel (written by k_reduce / k_fold_* of this round).
     // Only tile 0 writes the control block here, and nothing it writes is read
     // by the other tiles except status, whose change (run finished or failed)
     // also tells them to do nothing.
+    RunCtl* ctl = R.ctl;
+    const int32_t status = ctl->status;
     const unsigned long long key = ctl->maxkey;
     const bool bad = ctl->bad != 0;
     const bool resample = ctl->active != 0;
     const uint32_t U = ctl->u;
-    const double M = key_value(key);
-    const bool usable = !bad && key != 0 && M != -__builtin_huge_val();
     const uint32_t N = R.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ double s_wave[kRedThreads / 64];
     __shared__ double s_wave2[kRedThreads / 64];
     __shared__ double s_wave3[kRedThreads / 64];
 
+    // The tile's log-weights and the tile sums are requested before the control
+    // block is consumed, so all these loads are in flight together; when the
+    // round turns out not to resample they are simply not used.
+    const uint32_t tile0 = tr.tile * kTileRed;
+    const uint32_t first = tile0 + threadIdx.x * kRedItems;
+    double x[kRedItems];
+#pragma unroll
+    for (int k = 0; k < kRedItems; ++k) x[k] = first + k < N ? R.lw[first + k] : 0.0;
+    constexpr int kPer = (int)(kMaxFusedPropTiles * kPropThreads / kTileRed / kRedThreads);
+    double qv[kPer], ev[kPer];
+    if (R.fused) {
+        const uint32_t T = R.red_tiles;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const uint32_t t = threadIdx.x + (uint32_t)i * kRedThreads;
+            qv[i] = t < T ? R.part_q[t] : 0.0;
+            ev[i] = (tr.tile == 0 && t < T) ? R.part_e[t] : 0.0;
+        }
+    }
+
+    if (status != 0) return;  // uniform over the work-group
+    const double M = key_value(key);
+    const bool usable = !bad && key != 0 && M != -__builtin_huge_val();
+
     double base = 0.0, Qtot = 0.0;
     if (R.fused) {
         // every work-group folds the run's tile sums: total mass and own offset
-        const uint32_t T = R.red_tiles;
+        // (the sums are meaningless when the round is not usable)
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            qv[i] = usable ? qv[i] : 0.0;
+            ev[i] = usable ? ev[i] : 0.0;
+        }
         double q_all = 0.0, q_before = 0.0, e_all = 0.0;
-        if (usable) {
-            for (uint32_t t = threadIdx.x; t < T; t += kRedThreads) {
-                const double q = R.part_q[t];
-                q_all += q;
-                if (t < tr.tile) q_before += q;
-                if (tr.tile == 0) e_all += R.part_e[t];
-            }
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const uint32_t t = threadIdx.x + (uint32_t)i * kRedThreads;
+            q_all += qv[i];
+            if (t < tr.tile) q_before += qv[i];
+            e_all += ev[i];
         }
         q_all = wave_sum(q_all);
         q_before = wave_sum(q_before);
@@ -515,14 +637,11 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
 
     const double scale = (double)(1ull << grid_bits(N));
     const double rQ = 1.0 / Qtot;
-    const uint32_t tile0 = tr.tile * kTileRed;
-    const uint32_t first = tile0 + threadIdx.x * kRedItems;
     double q[kRedItems];
     double tsum = 0.0;
 #pragma unroll
     for (int k = 0; k < kRedItems; ++k) {
-        const uint32_t i = first + k;
-        q[k] = i < N ? __builtin_rint(fn::exp(R.lw[i] - M) * scale) : 0.0;
+        q[k] = first + k < N ? __builtin_rint(fn::exp(x[k] - M) * scale) : 0.0;
         tsum += q[k];
     }
     // inclusive scan of thread sums across the work-group (exact: integer-valued)
@@ -560,6 +679,18 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
     }
 }
 
+__global__ __launch_bounds__(kRedThreads) void k_scan_anc_one(const RunDev R)
+{
+    scan_anc_body(R, TileRef{0u, blockIdx.x});
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restrict__ runs,
+                                                           const TileRef* __restrict__ tiles)
+{
+    const TileRef tr = tiles[blockIdx.x];
+    scan_anc_body(runs[tr.run], tr);
+}
+
 // ---------------------------------------------------------------------------
 // Standalone pieces: max of a given weight vector, reads, self-tests, setup.
 // ---------------------------------------------------------------------------
@@ -578,7 +709,7 @@ __global__ __launch_bounds__(kPropThreads) void k_maxkey(const RunDev* __restric
     }
     const Partial r = block_partial<kPropThreads>(p);
     if (threadIdx.x == 0) {
-        R.part_key[tr.tile] = r.key;
+        R.part_key[tr.tile] = r.bad ? kBadKey : r.key;
         R.part_cnt[tr.tile] = r.act | (r.bad << 31);
         R.part_steps[tr.tile] = 0;
     }
@@ -637,8 +768,8 @@ __global__ void k_selftest_philox(const uint32_t* __restrict__ ctr, const uint32
 __global__ void k_reset(RunDev* run, uint64_t seed)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    run->seed = seed;
     RunCtl* c = run->ctl;
+    c->seed = seed;
     c->maxkey = 0;
     c->block_steps = 0;
     c->log_z = 0.0;
@@ -686,6 +817,30 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     else if (kind == 2) hipLaunchKernelGGL((k_propagate<2, double>), g, b, 0, st, runs, tiles);
     else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate<3, float>), g, b, 0, st, runs, tiles);
     else hipLaunchKernelGGL((k_propagate<3, double>), g, b, 0, st, runs, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipStream_t st)
+{
+    dim3 g(run.prop_tiles), b(kPropThreads);
+    if (kind == 0) hipLaunchKernelGGL((k_propagate_one<0, double>), g, b, 0, st, run);
+    else if (kind == 1 && precision == 32) hipLaunchKernelGGL((k_propagate_one<1, float>), g, b, 0, st, run);
+    else if (kind == 1) hipLaunchKernelGGL((k_propagate_one<1, double>), g, b, 0, st, run);
+    else if (kind == 2 && precision == 32) hipLaunchKernelGGL((k_propagate_one<2, float>), g, b, 0, st, run);
+    else if (kind == 2) hipLaunchKernelGGL((k_propagate_one<2, double>), g, b, 0, st, run);
+    else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate_one<3, float>), g, b, 0, st, run);
+    else hipLaunchKernelGGL((k_propagate_one<3, double>), g, b, 0, st, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_one(const RunDev& run, const RunDev* run_dev, hipStream_t st, int part)
+{
+    // part: 1 = reduction (+ fold), 2 = scan and ancestors, 3 = both
+    if (part & 1) {
+        hipLaunchKernelGGL(k_reduce_one, dim3(run.red_tiles), dim3(kRedThreads), 0, st, run);
+        if (!run.fused) hipLaunchKernelGGL(k_fold_sums, dim3(1), dim3(kFoldThreads), 0, st, run_dev);
+    }
+    if (part & 2) hipLaunchKernelGGL(k_scan_anc_one, dim3(run.red_tiles), dim3(kRedThreads), 0, st, run);
     return hipGetLastError();
 }
 

@@ -84,7 +84,7 @@ struct Lgssm {
 // observed branch above node `round` (preorder, left subtree first).
 // ---------------------------------------------------------------------------
 constexpr int kMaxDepthCap = 32;
-constexpr int kRegFrames = 4;  // frames held in registers on the fast path
+constexpr int kRegFrames = 3;  // frames held in registers on the fast path
 
 // Outcome of simulating one hidden lineage.
 enum Hidden : int { kDetected = 0, kUndetected = 1, kOverflow = 2 };
@@ -185,52 +185,77 @@ struct Crbd {
     struct State {
         double lambda, mu;
     };
-    // Stack: frame stack for hidden lineages; overflow is set when it ran out.
-    template <class Stack>
-    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
-                                         Stream& s, bool& ckpt, bool& overflow, Stack& stack)
+
+    // What a branch block knows before its hidden events are simulated.
+    struct Branch {
+        double tp, tc;  // ages of the parent and of the node
+        double ln1;     // -mu (t_p - t_c): no extinction along the branch
+        double ln2;     // log lambda (speciation at an internal node) or log rho (sampled tip)
+        int n;          // hidden speciations on the branch (-1: beyond the event cap)
+    };
+
+    // First part of a block: the init block entirely, or a branch block up to
+    // (and including) the Poisson draw of its hidden speciations.
+    __device__ static inline uint8_t begin(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
+                                           Stream& s, Branch& br)
     {
-        ckpt = true;
         if (b == 0) {
             const double lambda = m.p[3] > 0.0 ? m.p[3] : draw_gamma1(s, m.p[1]);
             const double mu = m.p[4] >= 0.0 ? m.p[4] : draw_gamma1(s, m.p[2]);
             st.lambda = (double)(Real)lambda;
             st.mu = (double)(Real)mu;
             lw = lw + m.corr;
+            br.n = 0;
+            br.ln1 = br.ln2 = 0.0;
             return m.n_nodes > 1 ? 1 : kStop;
         }
         const int node = (int)round;
-        const double tp = m.age[m.parent[node]];
-        const double tc = m.age[node];
-        const double ln1 = -st.mu * (tp - tc);
-        const double ln2 = m.left[node] >= 0 ? fn::log(st.lambda) : m.log_rho;
-        const int n = draw_poisson(s, st.lambda * (tp - tc));
-        double ln3 = 0.0;
-        if (n < 0) {
-            ln3 = -__builtin_huge_val();
-        } else {
-            CrbdSim sim{st.lambda, st.mu, m.p[0], 0, (int)m.p[5], (int)m.p[6]};
-            for (int e = 0; e < n; ++e) {
-                if (sim.events >= sim.max_events) {
-                    ln3 = -__builtin_huge_val();
-                    break;
-                }
-                sim.events += 1;
-                const double t = draw_uniform(s, tc, tp);
-                const int h = sim.template undetected<Stack>(s, t, stack);
-                if (h == kOverflow) {
-                    overflow = true;
-                    return b;
-                }
-                if (h == kDetected) {
-                    ln3 = -__builtin_huge_val();
-                    break;
-                }
-                ln3 = ln3 + m.ln2;
-            }
-        }
-        lw = lw + (ln1 + (ln2 + ln3));
+        br.tp = m.age[m.parent[node]];
+        br.tc = m.age[node];
+        br.ln1 = -st.mu * (br.tp - br.tc);
+        br.ln2 = m.left[node] >= 0 ? fn::log(st.lambda) : m.log_rho;
+        br.n = draw_poisson(s, st.lambda * (br.tp - br.tc));
         return node + 1 < m.n_nodes ? 1 : kStop;
+    }
+
+    // Second part of a branch block (simBranch): the n hidden speciations in
+    // order, each at a uniform time on the branch, each side lineage required
+    // to go undetected; returns ln3 (or sets overflow).
+    template <class Stack>
+    __device__ static inline double events(const ModelDev& m, double lambda, double mu, const Branch& br, Stream& s,
+                                           bool& overflow, Stack& stack)
+    {
+        if (br.n < 0) return -__builtin_huge_val();
+        double ln3 = 0.0;
+        CrbdSim sim{lambda, mu, m.p[0], 0, (int)m.p[5], (int)m.p[6]};
+        for (int e = 0; e < br.n; ++e) {
+            if (sim.events >= sim.max_events) return -__builtin_huge_val();
+            sim.events += 1;
+            const double t = draw_uniform(s, br.tc, br.tp);
+            const int h = sim.template undetected<Stack>(s, t, stack);
+            if (h == kOverflow) {
+                overflow = true;
+                return 0.0;
+            }
+            if (h == kDetected) return -__builtin_huge_val();
+            ln3 = ln3 + m.ln2;
+        }
+        return ln3;
+    }
+
+    // The whole block: lw += ln1 + (ln2 + ln3).
+    template <class Stack>
+    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
+                                         Stream& s, bool& ckpt, bool& overflow, Stack& stack)
+    {
+        ckpt = true;
+        Branch br;
+        const uint8_t next = begin(m, round, b, st, lw, s, br);
+        if (b == 0) return next;
+        const double ln3 = events<Stack>(m, st.lambda, st.mu, br, s, overflow, stack);
+        if (overflow) return b;
+        lw = lw + (br.ln1 + (br.ln2 + ln3));
+        return next;
     }
 };
 
