@@ -90,22 +90,78 @@ __device__ inline uint32_t offspring_before(double W, double Qtot, double rQ, ui
     return c;
 }
 
-template <class T>
-__device__ inline T wave_sum(T v)
+// Wavefront-wide scans and reductions with DPP row operations (the data moves
+// between lanes inside the VALU, with no LDS round trip). Inclusive scan:
+// shifts by 1, 2, 4, 8 within each row of 16 lanes, then the total of row r
+// is added to row r + 1 (row_bcast:15) and the total of rows 0-1 to rows 2-3
+// (row_bcast:31). Lanes outside the row mask or reading past a row start get
+// the identity (0). The combination order is fixed, so results are
+// reproducible. Every lane of the wavefront must be active.
+enum : int { kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118,
+             kRowBcast15 = 0x142, kRowBcast31 = 0x143 };
+
+template <int kCtrl, int kRowMask>
+__device__ inline uint32_t dpp_u32(uint32_t v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, true);
+}
+template <int kCtrl, int kRowMask>
+__device__ inline unsigned long long dpp_u64(unsigned long long v)
+{
+    const uint32_t lo = dpp_u32<kCtrl, kRowMask>((uint32_t)v);
+    const uint32_t hi = dpp_u32<kCtrl, kRowMask>((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+template <int kCtrl, int kRowMask>
+__device__ inline double dpp_f64(double v)
+{
+    return __longlong_as_double((long long)dpp_u64<kCtrl, kRowMask>((unsigned long long)__double_as_longlong(v)));
+}
+
+struct OpAddF64 {
+    static __device__ inline double op(double a, double b) { return a + b; }
+    template <int C, int M>
+    static __device__ inline double mv(double v) { return dpp_f64<C, M>(v); }
+};
+struct OpAddU32 {
+    static __device__ inline uint32_t op(uint32_t a, uint32_t b) { return a + b; }
+    template <int C, int M>
+    static __device__ inline uint32_t mv(uint32_t v) { return dpp_u32<C, M>(v); }
+};
+struct OpMaxU64 {
+    static __device__ inline unsigned long long op(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+    template <int C, int M>
+    static __device__ inline unsigned long long mv(unsigned long long v) { return dpp_u64<C, M>(v); }
+};
+
+template <class Op, class T>
+__device__ inline T wave_incl_scan(T v)
+{
+    v = Op::op(v, Op::template mv<kRowShr1, 0xf>(v));
+    v = Op::op(v, Op::template mv<kRowShr2, 0xf>(v));
+    v = Op::op(v, Op::template mv<kRowShr4, 0xf>(v));
+    v = Op::op(v, Op::template mv<kRowShr8, 0xf>(v));
+    v = Op::op(v, Op::template mv<kRowBcast15, 0xa>(v));
+    v = Op::op(v, Op::template mv<kRowBcast31, 0xc>(v));
     return v;
 }
 
+__device__ inline uint32_t lane63_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
+__device__ inline unsigned long long lane63_u64(unsigned long long v)
+{
+    return ((unsigned long long)lane63_u32((uint32_t)(v >> 32)) << 32) | lane63_u32((uint32_t)v);
+}
+
+// Totals, the same in every lane.
+__device__ inline double wave_sum(double v)
+{
+    v = wave_incl_scan<OpAddF64>(v);
+    return __longlong_as_double((long long)lane63_u64((unsigned long long)__double_as_longlong(v)));
+}
+__device__ inline uint32_t wave_sum(uint32_t v) { return lane63_u32(wave_incl_scan<OpAddU32>(v)); }
 __device__ inline unsigned long long wave_max_u64(unsigned long long v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
+    return lane63_u64(wave_incl_scan<OpMaxU64>(v));
 }
 
 // Key stored for a tile that produced a NaN or +inf log-weight: above every
@@ -153,7 +209,7 @@ __device__ inline Partial wave_partial(Partial p)
 {
     p.key = wave_max_u64(p.key);
     p.act = wave_sum(p.act);
-    p.bad = wave_sum(p.bad) ? 1u : 0u;
+    p.bad = __ballot(p.bad != 0) ? 1u : 0u;
     p.steps = wave_sum(p.steps);
     return p;
 }
@@ -519,12 +575,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __rest
             q_local += R.part_q[t];
             e_local += R.part_e[t];
         }
-    double q_incl = q_local;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double o = __shfl_up(q_incl, off, 64);
-        if (lane >= off) q_incl += o;
-    }
+    const double q_incl = wave_incl_scan<OpAddF64>(q_local);  // exact: integer-valued
     const double e_wave = wave_sum(e_local);
     __shared__ double s_qw[kFoldThreads / 64], s_ew[kFoldThreads / 64];
     if (lane == 63) s_qw[wave] = q_incl;
@@ -645,12 +696,7 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
         tsum += q[k];
     }
     // inclusive scan of thread sums across the work-group (exact: integer-valued)
-    double incl = tsum;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-    }
+    const double incl = wave_incl_scan<OpAddF64>(tsum);
     __shared__ uint32_t s_c[kTileRed];
     __shared__ uint32_t s_o0;
     if (lane == 63) s_wave[wave] = incl;
@@ -668,14 +714,36 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     const uint32_t count = (N - tile0) < (uint32_t)kTileRed ? (N - tile0) : (uint32_t)kTileRed;
     const uint32_t o0 = s_o0;
     const uint32_t o1 = s_c[count - 1];
-    for (uint32_t jj = o0 + threadIdx.x; jj < o1; jj += kRedThreads) {
-        uint32_t lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_c[mid] > jj) hi = mid;
-            else lo = mid + 1;
+    // Output slot jj descends from the first particle of the tile whose
+    // running offspring count exceeds jj. Each thread resolves four slots per
+    // pass with interleaved binary searches (count <= kTileRed = 2^10, so ten
+    // halvings always suffice).
+    constexpr int kSearch = 4;
+    static_assert(kTileRed <= 1024, "ten halvings cover the tile");
+    for (uint32_t b = o0 + threadIdx.x; b < o1; b += kSearch * kRedThreads) {
+        uint32_t lo[kSearch], hi[kSearch];
+#pragma unroll
+        for (int s = 0; s < kSearch; ++s) {
+            lo[s] = 0;
+            hi[s] = count - 1;
         }
-        R.anc[jj] = tile0 + lo;
+#pragma unroll
+        for (int it = 0; it < 10; ++it) {
+#pragma unroll
+            for (int s = 0; s < kSearch; ++s) {
+                const uint32_t jj = b + (uint32_t)s * kRedThreads;
+                const bool open = lo[s] < hi[s];
+                const uint32_t mid = (lo[s] + hi[s]) >> 1;
+                const bool right = s_c[mid] <= jj;
+                lo[s] = (open && right) ? mid + 1 : lo[s];
+                hi[s] = (open && !right) ? mid : hi[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < kSearch; ++s) {
+            const uint32_t jj = b + (uint32_t)s * kRedThreads;
+            if (jj < o1) R.anc[jj] = tile0 + lo[s];
+        }
     }
 }
 
