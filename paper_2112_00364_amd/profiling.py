@@ -5,6 +5,8 @@ This module turns one into the short text records kept with the benchmark:
 
 * ``trace``: per-kernel launch count and durations from a ``--kernel-trace``
   run, as a markdown table;
+* ``counters``: per-kernel means of every counter of one ``--pmc`` run, per
+  dispatch and per wavefront, as a markdown table;
 * ``traffic``: HBM bytes per launch from two ``--pmc`` runs (``FETCH_SIZE``,
   then ``WRITE_SIZE``, KiB per dispatch). Each counter is scaled by what it
   reads for a device-to-device copy of known size in the same run (the
@@ -13,6 +15,7 @@ This module turns one into the short text records kept with the benchmark:
 
 Usage:
   python -m paper_2112_00364_amd.profiling trace DB OUT.md --cmd "COMMAND"
+  python -m paper_2112_00364_amd.profiling counters DB OUT.md --cmd "COMMAND"
   python -m paper_2112_00364_amd.profiling traffic FETCH_DB WRITE_DB OUT.json \
       --cmd-fetch "COMMAND" --cmd-write "COMMAND" --source-sha SHA
 """
@@ -82,6 +85,37 @@ def counter_per_dispatch(db: str, counter: str):
     return [(d, names[d], acc[d]) for d in sorted(acc)]
 
 
+def counters_markdown(db: str, title: str, cmd: str) -> str:
+    """Mean of each counter per dispatch (and per wavefront when SQ_WAVES was
+    collected) for the library's kernels."""
+    con = sqlite3.connect(db)
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = {}
+    for d, k, c, v in con.execute("select dispatch_id, kernel_name, counter_name, value from counters_collection"):
+        if bench_kernel(k) is None:
+            continue
+        per[d][c] += v
+        names[d] = short_name(k)
+    by_kernel = collections.defaultdict(list)
+    for d in per:
+        by_kernel[names[d]].append(per[d])
+    counters = sorted({c for d in per for c in per[d]})
+    out = [f"# rocprofv3 counters: {title}", "", "Command (repository root):", "", "```", cmd, "```", "",
+           "Mean per dispatch (per wavefront in brackets when SQ_WAVES was collected).", "",
+           "| kernel | dispatches | " + " | ".join(counters) + " |", "|---|---|" + "---|" * len(counters)]
+    for name, ds in sorted(by_kernel.items()):
+        mean = {c: sum(d.get(c, 0.0) for d in ds) / len(ds) for c in counters}
+        waves = mean.get("SQ_WAVES", 0.0)
+        cells = []
+        for c in counters:
+            cell = f"{mean[c]:.4g}"
+            if waves > 0 and c.startswith("SQ_") and c not in ("SQ_WAVES", "SQ_BUSY_CYCLES"):
+                cell += f" ({mean[c] / waves:.4g})"
+            cells.append(cell)
+        out.append(f"| {name} | {len(ds)} | " + " | ".join(cells) + " |")
+    return "\n".join(out) + "\n"
+
+
 def calibration_scale(rows) -> float:
     """Bytes per counter unit: the known copy size over the largest copy dispatch's reading."""
     copies = [v for _, k, v in rows if short_name(k) == CALIBRATION_KERNEL]
@@ -121,6 +155,11 @@ def main(argv=None):
     t.add_argument("out")
     t.add_argument("--cmd", required=True)
     t.add_argument("--title", default=None)
+    c = sub.add_parser("counters")
+    c.add_argument("db")
+    c.add_argument("out")
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--title", default=None)
     f = sub.add_parser("traffic")
     f.add_argument("fetch_db")
     f.add_argument("write_db")
@@ -129,9 +168,10 @@ def main(argv=None):
     f.add_argument("--cmd-write", required=True)
     f.add_argument("--source-sha", required=True)
     a = ap.parse_args(argv)
-    if a.what == "trace":
+    if a.what in ("trace", "counters"):
         title = a.title or a.out.rsplit("/", 1)[-1].rsplit(".", 1)[0]
-        text = trace_markdown(a.db, title, a.cmd)
+        make = trace_markdown if a.what == "trace" else counters_markdown
+        text = make(a.db, title, a.cmd)
         open(a.out, "w").write(text)
         print(text)
     else:
