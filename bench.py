@@ -9,7 +9,10 @@ memory before timing starts and every run's buffers are allocated beforehand.
 Printed: one JSON line with canonical particle-block-steps/s (block executions
 excluding b_stop, per second of wall time of the timed runs), the dominant
 kernel's achieved bandwidth against MI355X's HBM peak, and the CPU oracle's
-throughput on a bounded sample of the same workload.
+throughput on a bounded sample of the same workload. Beside the headline: the
+same workload at 2^24 particles (buffers beyond the Infinity Cache), 512
+batched ClaDS runs of 4096 particles, and a serving stream (one-at-a-time vs
+continuous batching, p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -112,26 +115,54 @@ def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16):
             "block_steps_per_s": total / dt, "finished_runs": ok, "rounds_per_tick": rounds_per_tick}
 
 
-def serving(ctx, smc, n_requests: int, budget_bytes: int):
-    """Serving stream: calibrate the one-at-a-time service rate, then replay the
-    same requests with Poisson arrivals at 0.9 x that rate through (a) FIFO
-    one-at-a-time plain runs and (b) continuous batching."""
+def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers):
+    """Serving stream: calibrate the one-at-a-time service rate on the first
+    requests, then for each multiplier m replay the same requests with Poisson
+    arrivals at m x that rate through (a) FIFO one-at-a-time plain runs and
+    (b) continuous batching."""
     from paper_2112_00364_amd import serve as S
     reqs = S.make_requests(n_requests, 5000, rate_per_s=1.0)
     calib = reqs[: min(32, len(reqs))]
     _, t_cal = S.serve_one_at_a_time(ctx, calib, honour_arrivals=False)
     rate = len(calib) / t_cal
-    arr = 0.9 * rate
-    S.rescale_arrivals(reqs, arr, 5001)
-    print(f"serving: one-at-a-time rate {rate:.2f}/s, arrivals at {arr:.2f}/s", file=sys.stderr, flush=True)
-    base, t_base = S.serve_one_at_a_time(ctx, reqs)
-    bat, t_bat = S.serve_batched(ctx, reqs, budget_bytes)
-    sb, sbb = S.summarize(base, t_base), S.summarize(bat, t_bat)
-    same = {r["id"]: r["log_z"] for r in base}
-    worst = max(abs(r["log_z"] - same[r["id"]]) / max(1.0, abs(same[r["id"]])) for r in bat)
-    return {"requests": n_requests, "arrival_rate_per_s": arr, "one_at_a_time_service_rate_per_s": rate,
-            "one_at_a_time": sb, "batched": sbb, "max_rel_logz_diff_batched_vs_alone": worst,
-            "memory_budget_bytes": budget_bytes}
+    out = {"requests": n_requests, "one_at_a_time_service_rate_per_s": rate, "memory_budget_bytes": budget_bytes,
+           "by_arrival_rate": []}
+    for m in multipliers:
+        arr = m * rate
+        S.rescale_arrivals(reqs, arr, 5001)
+        print(f"serving: one-at-a-time rate {rate:.2f}/s, arrivals at {arr:.2f}/s", file=sys.stderr, flush=True)
+        base, t_base = S.serve_one_at_a_time(ctx, reqs)
+        bat, t_bat = S.serve_batched(ctx, reqs, budget_bytes)
+        same = {r["id"]: r["log_z"] for r in base}
+        worst = max(abs(r["log_z"] - same[r["id"]]) / max(1.0, abs(same[r["id"]])) for r in bat)
+        out["by_arrival_rate"].append({"multiplier": m, "arrival_rate_per_s": arr,
+                                       "one_at_a_time": S.summarize(base, t_base),
+                                       "batched": S.summarize(bat, t_bat),
+                                       "max_rel_logz_diff_batched_vs_alone": worst})
+    return out
+
+
+def large_point(smc, model, n: int, runs: int = 2):
+    """Complete runs at a particle count whose buffers exceed the 256 MB
+    Infinity Cache, so every round streams from HBM."""
+    import torch
+    run = smc.Run(model, n, 77)
+    run.run_to_end()
+    torch.cuda.synchronize()
+    stream = model.ctx.stream
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for i in range(runs):
+        run.reset(78 + i)
+        assert run.run_to_end() == smc.FINISHED
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / runs
+    s = run.stats()
+    run.close()
+    return {"particles": n, "runs": runs, "ms_per_run": ms, "block_steps_per_run": s["block_steps"],
+            "block_steps_per_s": s["block_steps"] / (ms / 1e3)}
 
 
 def main():
@@ -144,7 +175,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-run batched ClaDS leg")
-    ap.add_argument("--serving-requests", type=int, default=2000, help="0 skips the serving leg")
+    ap.add_argument("--serving-requests", type=int, default=250,
+                    help="requests in the serving leg (0 skips it; the full stream is 2000)")
+    ap.add_argument("--serving-rates", default="0.9",
+                    help="arrival rates as multiples of the one-at-a-time service rate, comma-separated")
+    ap.add_argument("--no-large", action="store_true", help="skip the 2^24-particle point")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -249,6 +284,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "particle_rounds_per_s": N_PARTICLES * rounds * args.steps / (gpu_ms / 1e3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -262,12 +298,16 @@ def main():
         "wall_s_timed": wall,
         "log_z": log_zs,
     }
+    if not args.no_large:
+        print("2^24-particle point", file=sys.stderr, flush=True)
+        out["large"] = large_point(smc, model, 1 << 24)
     if not args.no_batched:
         print("batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_clads(ctx, smc, I)
     if args.serving_requests > 0:
         print("serving leg", file=sys.stderr, flush=True)
-        out["serving"] = serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30))
+        rates = [float(x) for x in args.serving_rates.split(",") if x]
+        out["serving"] = serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30), rates)
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_particles)
