@@ -107,9 +107,6 @@ struct smc_run {
     uint64_t n = 0, seed = 0;
     RunDev host{};
     RunDev* dev = nullptr;
-    std::vector<TileRef> prop_tiles_h, red_tiles_h;
-    TileRef* prop_tiles = nullptr;
-    TileRef* red_tiles = nullptr;
     uint32_t n_prop = 0, n_red = 0;
     bool expect_step = true;   // Alg. 1: step 2 and step 3 alternate
     uint32_t rounds_issued = 0;
@@ -157,6 +154,12 @@ smc_status read_ctl(smc_run* r, RunCtl* out)
 size_t real_bytes(const smc_model* m) { return m->precision == 32 ? 4 : 8; }
 
 // Allocate and initialise a run's device state (Alg. 1 step 1).
+void set_prop_tiles(RunDev& h)
+{
+    h.prop_tiles = (uint32_t)((h.n + kPropThreads - 1) / kPropThreads);
+    h.fused = h.prop_tiles <= kMaxFusedPropTiles ? 1u : 0u;
+}
+
 smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
 {
     smc_ctx* ctx = m->ctx;
@@ -180,8 +183,7 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     }
     h.lw = (double*)get(n * 8);
     h.anc = (uint32_t*)get(n * 4);
-    h.prop_tiles = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
-    h.fused = h.prop_tiles <= kMaxFusedPropTiles ? 1u : 0u;
+    set_prop_tiles(h);
     if (m->kind == SMC_MODEL_CLADS) h.side_stack = get((size_t)kMaxDepthCap * n * 17);
     h.part_key = (unsigned long long*)get(h.prop_tiles * 8);
     h.part_cnt = (uint32_t*)get(h.prop_tiles * 4);
@@ -192,10 +194,8 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     r->dev = (RunDev*)get(sizeof(RunDev));
     r->n_prop = h.prop_tiles;
     r->n_red = h.red_tiles;
-    r->prop_tiles = (TileRef*)get(sizeof(TileRef) * r->n_prop);
-    r->red_tiles = (TileRef*)get(sizeof(TileRef) * r->n_red);
     bool ok = h.ctl && h.lw && h.anc && h.part_q && h.part_key && h.part_cnt && h.part_steps &&
-              (h.side_stack || m->kind != SMC_MODEL_CLADS) && h.part_e && h.prefix && r->dev && r->prop_tiles && r->red_tiles;
+              (h.side_stack || m->kind != SMC_MODEL_CLADS) && h.part_e && h.prefix && r->dev;
     for (int b = 0; b < 2; ++b) {
         ok = ok && h.buf[b].blk;
         for (int f = 0; f < real_fields(m->kind); ++f) ok = ok && h.buf[b].real[f];
@@ -206,18 +206,9 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
         r->arena.release_all();
         return fail(SMC_ERR_OOM, "device allocation failed for a run of " + std::to_string(n) + " particles");
     }
-    r->prop_tiles_h.resize(r->n_prop);
-    r->red_tiles_h.resize(r->n_red);
-    for (uint32_t t = 0; t < r->n_prop; ++t) r->prop_tiles_h[t] = TileRef{0, t};
-    for (uint32_t t = 0; t < r->n_red; ++t) r->red_tiles_h[t] = TileRef{0, t};
     hipStream_t st = ctx->stream;
     HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, st));
     HIP_TRY(launch_reset(r->dev, seed, st));  // control block: round 0, log Z 0, the seed
-    HIP_TRY(hipMemcpyAsync(r->prop_tiles, r->prop_tiles_h.data(), sizeof(TileRef) * r->n_prop,
-                           hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(r->red_tiles, r->red_tiles_h.data(), sizeof(TileRef) * r->n_red,
-                           hipMemcpyHostToDevice, st));
-    // the host copies above live in the run object until it is destroyed
     return SMC_OK;
 }
 
@@ -677,8 +668,7 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     RunDev h{};
     h.n = (uint32_t)n;
     h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
-    h.prop_tiles = (uint32_t)((n + kPropThreads - 1) / kPropThreads);
-    h.fused = h.prop_tiles <= kMaxFusedPropTiles ? 1u : 0u;
+    set_prop_tiles(h);
     h.lw = const_cast<double*>(lw);
     h.anc = anc;
     h.ctl = (RunCtl*)arena.get(sizeof(RunCtl));

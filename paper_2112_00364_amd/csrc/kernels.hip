@@ -90,6 +90,17 @@ __device__ inline uint32_t offspring_before(double W, double Qtot, double rQ, ui
     return c;
 }
 
+// Values every lane of a work-group reads from a run's control block are
+// uniform; moving them to scalar registers keeps the address arithmetic that
+// depends on them (the parity-selected particle buffer, for one) out of
+// vector registers.
+__device__ inline uint32_t uniform_u32(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ inline int32_t uniform_i32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline unsigned long long uniform_u64(unsigned long long v)
+{
+    return ((unsigned long long)uniform_u32((uint32_t)(v >> 32)) << 32) | uniform_u32((uint32_t)v);
+}
+
 // Wavefront-wide scans and reductions with DPP row operations (the data moves
 // between lanes inside the VALU, with no LDS round trip). Inclusive scan:
 // shifts by 1, 2, 4, 8 within each row of 16 lanes, then the total of row r
@@ -390,12 +401,12 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
 {
     const uint32_t j = tile * kPropThreads + threadIdx.x;
     const bool valid = j < R.n;
+    RunCtl* ctl = R.ctl;
+    const int32_t status = uniform_i32(ctl->status);
+    const uint32_t round = uniform_u32(ctl->round);
+    const uint64_t seed = uniform_u64(ctl->seed);
     // The ancestor index is loaded before the control block is consumed, so
     // the two loads overlap (at round 0 the value is not used).
-    RunCtl* ctl = R.ctl;
-    const int32_t status = ctl->status;
-    const uint32_t round = ctl->round;
-    const uint64_t seed = ctl->seed;
     const uint32_t ancestor = valid ? R.anc[j] : 0u;
     if (status != 0) return;  // uniform over the work-group
     __shared__ uint32_t s_arrived;
@@ -466,7 +477,7 @@ __device__ __forceinline__ void reduce_body(const RunDev& R, const TileRef tr)
     // The status, the tile's log-weights and the propagation partials are all
     // requested before any of them is used, so their latencies overlap.
     RunCtl* ctl = R.ctl;
-    const int32_t status = ctl->status;
+    const int32_t status = uniform_i32(ctl->status);
     double x[kRedItems];
     const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
 #pragma unroll
@@ -484,7 +495,7 @@ __device__ __forceinline__ void reduce_body(const RunDev& R, const TileRef tr)
             key = f.bad ? kBadKey : f.key;
         }
     } else {
-        key = ctl->bad ? kBadKey : ctl->maxkey;
+        key = uniform_u32(ctl->bad) ? kBadKey : uniform_u64(ctl->maxkey);
     }
     const double M = key_value(key);
     if (key == kBadKey || key == 0 || M == -__builtin_huge_val()) return;  // uniform over the work-group
@@ -611,11 +622,11 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     // by the other tiles except status, whose change (run finished or failed)
     // also tells them to do nothing.
     RunCtl* ctl = R.ctl;
-    const int32_t status = ctl->status;
-    const unsigned long long key = ctl->maxkey;
-    const bool bad = ctl->bad != 0;
-    const bool resample = ctl->active != 0;
-    const uint32_t U = ctl->u;
+    const int32_t status = uniform_i32(ctl->status);
+    const unsigned long long key = uniform_u64(ctl->maxkey);
+    const bool bad = uniform_u32(ctl->bad) != 0;
+    const bool resample = uniform_u32(ctl->active) != 0;
+    const uint32_t U = uniform_u32(ctl->u);
     const uint32_t N = R.n;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ double s_wave[kRedThreads / 64];
@@ -716,10 +727,11 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     const uint32_t o1 = s_c[count - 1];
     // Output slot jj descends from the first particle of the tile whose
     // running offspring count exceeds jj. Each thread resolves four slots per
-    // pass with interleaved binary searches (count <= kTileRed = 2^10, so ten
-    // halvings always suffice).
+    // pass with interleaved binary searches of kHalvings steps (count <=
+    // kTileRed <= 2^kHalvings, so that many halvings always suffice).
     constexpr int kSearch = 4;
-    static_assert(kTileRed <= 1024, "ten halvings cover the tile");
+    constexpr int kHalvings = kTileRed <= 1024 ? 10 : (kTileRed <= 2048 ? 11 : (kTileRed <= 4096 ? 12 : 13));
+    static_assert(kTileRed <= 8192, "the search length covers the tile");
     for (uint32_t b = o0 + threadIdx.x; b < o1; b += kSearch * kRedThreads) {
         uint32_t lo[kSearch], hi[kSearch];
 #pragma unroll
@@ -728,7 +740,7 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
             hi[s] = count - 1;
         }
 #pragma unroll
-        for (int it = 0; it < 10; ++it) {
+        for (int it = 0; it < kHalvings; ++it) {
 #pragma unroll
             for (int s = 0; s < kSearch; ++s) {
                 const uint32_t jj = b + (uint32_t)s * kRedThreads;
