@@ -41,6 +41,7 @@ class _Model(C.Structure):
         ("right", C.POINTER(C.c_int32)), ("age", C.POINTER(C.c_double)),
         ("T", C.c_int32), ("y", C.POINTER(C.c_double)),
         ("p", C.c_double * 16),
+        ("ess_threshold", C.c_double),
     ]
 
 
@@ -75,6 +76,8 @@ def lib():
     L.or_log_z.argtypes = [C.c_void_p]; L.or_log_z.restype = C.c_double
     L.or_round.argtypes = [C.c_void_p]; L.or_round.restype = C.c_uint32
     L.or_block_steps.argtypes = [C.c_void_p]; L.or_block_steps.restype = C.c_uint64
+    L.or_resamples.argtypes = [C.c_void_p]; L.or_resamples.restype = C.c_uint32
+    L.or_ess_resamples.argtypes = [f64p, C.c_uint64, C.c_double]; L.or_ess_resamples.restype = C.c_int32
     L.or_read.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]; L.or_read.restype = C.c_int32
     L.or_propagate_particle.argtypes = [C.POINTER(_Model), C.c_uint64, C.c_uint32, C.c_uint32,
                                         C.POINTER(C.c_uint8), f64p, f64p, C.POINTER(C.c_int32), f64p]
@@ -142,6 +145,12 @@ def systematic(lw, seed, rnd):
     return int(st), anc, inc.value, int(qtot.value)
 
 
+def ess_resamples(lw, threshold):
+    """The ESS rule on one log-weight vector: 1 resample, 0 carry, -1 invalid threshold."""
+    lw = np.ascontiguousarray(lw, dtype=np.float64)
+    return int(lib().or_ess_resamples(_ptr(lw, C.c_double), len(lw), float(threshold)))
+
+
 # --- runs -----------------------------------------------------------------
 
 def _model_struct(spec, keep):
@@ -167,6 +176,7 @@ def _model_struct(spec, keep):
         m.y = _ptr(y, C.c_double)
     for i, v in enumerate(spec.get("params", [])):
         m.p[i] = float(v)
+    m.ess_threshold = float(spec.get("ess_threshold", 0.0))
     return m
 
 
@@ -226,6 +236,7 @@ class Run:
         params = list(spec.get("params", []))
         for i, v in enumerate(params):
             m.p[i] = float(v)
+        m.ess_threshold = float(spec.get("ess_threshold", 0.0))
         self._m = m
         self.n = int(n)
         self.spec = spec
@@ -263,6 +274,10 @@ class Run:
     @property
     def block_steps(self):
         return int(lib().or_block_steps(self._h))
+
+    @property
+    def resamples(self):
+        return int(lib().or_resamples(self._h))
 
     @property
     def max_stack(self):

@@ -307,6 +307,8 @@ struct or_run {
     double* real[OR_MAX_FIELDS];
     int32_t* ints[OR_MAX_FIELDS];
     double* stack;             /* [n * stack_depth] */
+    uint32_t ess_t;            /* ESS threshold numerator over 2^16 (0: always resample) */
+    uint32_t resamples;        /* rounds that resampled */
     /* derived constants, computed once from the model parameters */
     double ln2, log_rho, corr, log_w, obs_c, obs_var;
     int tips;
@@ -592,7 +594,9 @@ or_run* or_create(const or_model* m, uint64_t n, uint64_t seed)
     if ((m->kind == OR_CRBD || m->kind == OR_CLADS) && (m->n_nodes < 1 || !m->parent || !m->age || !m->left))
         return NULL;
     if (m->kind == OR_LGSSM && (m->T < 1 || !m->y)) return NULL;
+    if (!(m->ess_threshold >= 0.0 && m->ess_threshold <= 1.0)) return NULL;
     or_run* r = (or_run*)calloc(1, sizeof *r);
+    r->ess_t = (uint32_t)nearbyint(m->ess_threshold * 65536.0);
     r->m = *m;
     r->n = n;
     r->seed = seed;
@@ -762,6 +766,44 @@ int32_t or_systematic(const double* lw, uint64_t n, uint64_t seed, uint32_t roun
 }
 
 /* ------------------------------------------------------------------------- */
+/* ESS-triggered resampling. Sec. 3.3 lists adaptive resampling on the        */
+/* effective sample size among RootPPL's features without fixing the rule;   */
+/* the reading here: the ESS is taken on the quantised weights of the        */
+/* resampling step, q_n = rint(exp(lw_n - M) 2^G),                            */
+/*   ESS = (sum q)^2 / sum q^2,                                               */
+/* and a round resamples iff ESS < t N / 2^16, t = rint(threshold 2^16),      */
+/* decided exactly in integers: 2^16 (sum q)^2 < t N sum q^2 (both sides are  */
+/* below 2^126 because N 2^G <= 2^53). t = 0 resamples every round.           */
+/* ------------------------------------------------------------------------- */
+static int ess_rule(const double* lw, uint64_t n, uint32_t t)
+{
+    if (t == 0) return 1;
+    double M = -INFINITY;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (lw[i] != lw[i] || lw[i] == INFINITY) return 1; /* the resampling step reports it */
+        if (lw[i] > M) M = lw[i];
+    }
+    if (M == -INFINITY) return 1;
+    int G = grid_bits(n);
+    uint64_t s1 = 0;
+    unsigned __int128 s2 = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t q = (uint64_t)nearbyint(ldexp(or_exp(lw[i] - M), G));
+        s1 += q;
+        s2 += (unsigned __int128)q * q;
+    }
+    unsigned __int128 lhs = (unsigned __int128)s1 * s1 * 65536u;
+    unsigned __int128 rhs = (unsigned __int128)t * n * s2;
+    return lhs < rhs;
+}
+
+int32_t or_ess_resamples(const double* lw, uint64_t n, double threshold)
+{
+    if (!(threshold >= 0.0 && threshold <= 1.0) || n == 0) return -1;
+    return ess_rule(lw, n, (uint32_t)nearbyint(threshold * 65536.0));
+}
+
+/* ------------------------------------------------------------------------- */
 /* Alg. 1 step 3 plus the log Z update (Sec. 3.3). When every particle is at */
 /* b_stop the run ends: the last weights still enter log Z, no resampling.   */
 /* ------------------------------------------------------------------------- */
@@ -770,13 +812,22 @@ int32_t or_resample(or_run* r)
     if (r->status != OR_OK) return r->status;
     int any_active = 0;
     for (uint64_t i = 0; i < r->n; ++i) any_active |= (r->blk[i] != OR_STOP);
+    /* While particles are still active, the ESS rule may keep the weights:
+     * no resampling, identity ancestors, log Z unchanged, weights carried. */
+    int resample = any_active && ess_rule(r->lw, r->n, r->ess_t);
     double inc = 0.0;
     uint64_t qtot = 0;
-    int32_t st = systematic_core(r->lw, r->n, r->seed, r->round, any_active, r->anc, &inc, &qtot);
+    int32_t st = systematic_core(r->lw, r->n, r->seed, r->round, resample, r->anc, &inc, &qtot);
     if (st == OR_DEGENERATE) { r->log_z = -INFINITY; r->status = st; return st; }
     if (st != OR_OK) { r->status = st; return st; }
+    if (!any_active) { r->log_z = r->log_z + inc; r->status = OR_FINISHED; return OR_FINISHED; }
+    if (!resample) {
+        for (uint64_t j = 0; j < r->n; ++j) r->anc[j] = (uint32_t)j;
+        r->round += 1;
+        return OR_OK;
+    }
     r->log_z = r->log_z + inc;
-    if (!any_active) { r->status = OR_FINISHED; return OR_FINISHED; }
+    r->resamples += 1;
     /* (s'_n, b'_n) = (s_{a_n}, b_{a_n}); weights reset. */
     uint64_t n = r->n;
     uint8_t* nb = (uint8_t*)malloc(n);
@@ -820,6 +871,7 @@ double or_log_z(const or_run* r) { return r->log_z; }
 int32_t or_status(const or_run* r) { return r->status; }
 uint32_t or_round(const or_run* r) { return r->round; }
 uint64_t or_block_steps(const or_run* r) { return r->block_steps; }
+uint32_t or_resamples(const or_run* r) { return r->resamples; }
 int32_t or_max_stack(const or_run* r) { return r->stack_depth; }
 
 /* Copy out per-particle arrays; real fields come out in the storage precision. */

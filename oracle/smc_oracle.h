@@ -47,6 +47,7 @@ typedef struct {
     int32_t T;               /* state-space models: number of observations */
     const double* y;         /* [T] */
     double p[16];            /* model parameters, meaning per kind */
+    double ess_threshold;    /* 0: resample every round; (0, 1]: ESS-triggered (see or_ess_resamples) */
 } or_model;
 
 typedef struct or_run or_run;
@@ -64,6 +65,9 @@ int64_t or_poisson_words(double m, const uint32_t* words, int32_t n_words, int32
 void or_ancestors(const uint64_t* Q, uint64_t n, uint32_t U, uint32_t* anc);
 int32_t or_systematic(const double* lw, uint64_t n, uint64_t seed, uint32_t round,
                       uint32_t* anc, double* logz_increment, uint64_t* qtot_units);
+/* The ESS rule on a log-weight vector: 1 = resample, 0 = carry the weights.
+ * -1 when the threshold is outside [0, 1]. */
+int32_t or_ess_resamples(const double* lw, uint64_t n, double threshold);
 
 /* A run: Alg. 1 driven one step at a time. */
 or_run* or_create(const or_model* m, uint64_t n, uint64_t seed);
@@ -75,6 +79,7 @@ double or_log_z(const or_run* r);
 int32_t or_status(const or_run* r);
 uint32_t or_round(const or_run* r);
 uint64_t or_block_steps(const or_run* r);
+uint32_t or_resamples(const or_run* r);  /* rounds that resampled */
 int32_t or_read(const or_run* r, int32_t what, void* dst);
 int32_t or_max_stack(const or_run* r);
 int32_t or_propagate_particle(const or_model* m, uint64_t seed, uint32_t slot, uint32_t round,
