@@ -101,6 +101,16 @@ enum {
  *              sigma scale, max events, max depth, fixed lambda0 (>0),
  *              fixed eps (>=0), fixed alpha (>0), fixed sigma (>=0)}.
  * Hidden-event budgets must lie in [0, 10^6] and recursion depths in [1, 32].
+ * ess_threshold: 0 resamples every round (Algorithm 1). A value tau in (0, 1]
+ *   turns on resampling triggered by the effective sample size (listed among
+ *   RootPPL's features in Sec. 3.3): after each propagation the ESS is taken on
+ *   the quantised weights q of the resampling step, ESS = (sum q)^2 / sum q^2,
+ *   and the round resamples iff ESS < t N / 2^16 with t = rint(tau 2^16)
+ *   (decided exactly in integers). A round that does not resample keeps the
+ *   log-weights (the next propagation adds to them), takes the identity as
+ *   ancestors and leaves log Z unchanged; the next resampling, or the end of
+ *   the run, folds the carried weights into log Z. Values outside [0, 1] are
+ *   rejected.
  * Trees (CRBD, CLADS): n_nodes = 2 tips - 1 nodes in preorder, root 0, left
  * subtree first; parent[root] = -1, left/right = -1 at tips; age = time before
  * the present (tips 0). */
@@ -116,6 +126,7 @@ typedef struct {
     int32_t T;
     const double* y;
     double params[16];
+    double ess_threshold;
 } smc_model_desc;
 
 /* Context: one device, one stream. stream is a hipStream_t (NULL = the null
@@ -139,7 +150,9 @@ smc_status smc_step(smc_run* run);
 /* Algorithm 1 step 3: log Z update, systematic ancestors, and the gather of
  * (state, block) by ancestor (performed on read by the next smc_step). When
  * every particle is at b_stop, only the log Z update runs and the run
- * finishes. */
+ * finishes. With an ESS threshold, a round whose ESS is high enough skips the
+ * resampling and the log Z update and carries the weights (see
+ * smc_model_desc). */
 smc_status smc_resample(smc_run* run);
 
 /* Termination check (synchronises): *done = 1 when the run finished,
@@ -164,7 +177,8 @@ smc_status smc_reset(smc_run* run, uint64_t seed);
 
 /* Copy per-particle data to a caller-owned host buffer (synchronises).
  * what: SMC_READ_BLK (uint8 per particle; 255 = b_stop), SMC_READ_LW (double),
- * SMC_READ_ANC (uint32: ancestors of the last resampling), or
+ * SMC_READ_ANC (uint32: ancestors of the last smc_resample; the identity when
+ * the ESS rule kept the weights), or
  * SMC_READ_FIELD0 + k for state field k in the model's field order (real fields
  * in the storage precision, then int32 fields, then the ClaDS rate stack as
  * [particle][level] with smc_run_stats().stack_depth levels). State is returned
@@ -179,6 +193,7 @@ typedef struct {
     uint64_t block_steps;    /* executions of the model's blocks (b_stop excluded) */
     double log_z;
     int32_t stack_depth;     /* ClaDS: pending-rate stack levels per particle */
+    uint32_t resamples;      /* rounds that resampled (every round but the last without an ESS threshold) */
 } smc_stats;
 smc_status smc_run_stats(smc_run* run, smc_stats* out);
 

@@ -95,6 +95,7 @@ struct smc_model {
     smc_ctx* ctx = nullptr;
     int kind = 0, precision = 64, checkpoint = 1, n_nodes = 0, T = 0;
     int stack_depth = 0;
+    uint32_t ess_t = 0;              // ESS threshold numerator over 2^16 (0: resample every round)
     std::vector<int32_t> sp_before;  // ClaDS: stack size when node r is visited (index n_nodes = final)
     ModelDev host{};
     ModelDev* dev = nullptr;
@@ -191,11 +192,14 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     h.part_q = (double*)get(h.red_tiles * 8);
     h.part_e = (double*)get(h.red_tiles * 8);
     h.prefix = (double*)get(h.red_tiles * 8);
+    h.ess_t = m->ess_t;
+    if (h.ess_t) h.part_q2 = (unsigned long long*)get(h.red_tiles * 16);
     r->dev = (RunDev*)get(sizeof(RunDev));
     r->n_prop = h.prop_tiles;
     r->n_red = h.red_tiles;
     bool ok = h.ctl && h.lw && h.anc && h.part_q && h.part_key && h.part_cnt && h.part_steps &&
-              (h.side_stack || m->kind != SMC_MODEL_CLADS) && h.part_e && h.prefix && r->dev;
+              (h.side_stack || m->kind != SMC_MODEL_CLADS) && h.part_e && h.prefix && r->dev &&
+              (h.part_q2 || !h.ess_t);
     for (int b = 0; b < 2; ++b) {
         ok = ok && h.buf[b].blk;
         for (int f = 0; f < real_fields(m->kind); ++f) ok = ok && h.buf[b].real[f];
@@ -328,6 +332,8 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
     }
     if (d->kind == SMC_MODEL_LGSSM && (d->T < 1 || d->T > (1 << 24) || !d->y))
         return fail(SMC_ERR_INVALID, "observations missing");
+    if (!(d->ess_threshold >= 0.0 && d->ess_threshold <= 1.0))
+        return fail(SMC_ERR_INVALID, "ess_threshold must be in [0, 1]");
     smc_model* m = new (std::nothrow) smc_model();
     if (!m) return fail(SMC_ERR_OOM, "host allocation failed");
     m->ctx = ctx;
@@ -337,6 +343,7 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
     m->checkpoint = d->checkpoint;
     m->n_nodes = tree ? d->n_nodes : 0;
     m->T = d->kind == SMC_MODEL_LGSSM ? d->T : 0;
+    m->ess_t = (uint32_t)std::nearbyint(d->ess_threshold * 65536.0);
     ModelDev& h = m->host;
     h.kind = d->kind;
     h.precision = d->precision;
@@ -539,9 +546,11 @@ smc_status smc_read(smc_run* r, int32_t what, void* dst, size_t bytes)
     const uint64_t n = r->n;
     hipStream_t st = r->ctx->stream;
     if (r->rounds_issued == 0 && r->expect_step) return fail(SMC_ERR_STATE, "nothing propagated yet");
-    // Where the newest state lives, and whether it still waits for its gather.
-    const bool pending_gather = r->expect_step && c.status == SMC_OK;
-    const uint32_t last_round = pending_gather ? c.round - 1 : c.round;
+    // Where the newest state lives, and whether it still waits for its gather
+    // (a round that kept its weights under the ESS rule has nothing to gather).
+    const bool resampled_pending = r->expect_step && c.status == SMC_OK;
+    const bool pending_gather = resampled_pending && !c.carry;
+    const uint32_t last_round = resampled_pending ? c.round - 1 : c.round;
     const ParticleBuf& b = r->host.buf[last_round & 1u];
     const uint32_t* anc = pending_gather ? r->host.anc : nullptr;
     auto fetch = [&](const void* src, int elem, uint64_t levels) -> smc_status {
@@ -569,6 +578,11 @@ smc_status smc_read(smc_run* r, int32_t what, void* dst, size_t bytes)
     }
     if (what == SMC_READ_ANC) {
         if (bytes < n * 4) return fail(SMC_ERR_INVALID, "destination too small");
+        if (c.carry) {  // the last smc_resample kept the weights: identity ancestors
+            uint32_t* o = (uint32_t*)dst;
+            for (uint64_t i = 0; i < n; ++i) o[i] = (uint32_t)i;
+            return SMC_OK;
+        }
         HIP_TRY(hipMemcpyAsync(dst, r->host.anc, n * 4, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         return SMC_OK;
@@ -622,6 +636,7 @@ smc_status smc_run_stats(smc_run* r, smc_stats* out)
     out->block_steps = c.block_steps;
     out->log_z = c.log_z;
     out->stack_depth = r->model->stack_depth;
+    out->resamples = c.resamples;
     return SMC_OK;
 }
 

@@ -18,9 +18,10 @@ struct alignas(64) RunCtl {
     int32_t status;                  // SMC_OK / FINISHED / ERR_NAN / DEGENERATE
     uint32_t active;                 // particles not at b_stop after this round's propagation
     uint32_t bad;                    // a NaN or +inf log-weight was produced
-    uint32_t pad0;
+    uint32_t carry;                  // 1: the last round kept its weights (ESS rule), no gather pending
     unsigned long long seed;         // Philox key of the run (set by init / reset)
-    uint32_t pad[2];
+    uint32_t resamples;              // rounds that resampled
+    uint32_t pad;
 };
 
 // One particle buffer: block index, real fields (storage precision), int
@@ -37,6 +38,8 @@ struct RunDev {
     uint32_t red_tiles;            // reduction / scan tiles of kTileRed particles
     uint32_t prop_tiles;           // propagation tiles of kPropThreads particles
     uint32_t fused;                // 1: the reduction and scan fold the partials themselves
+    uint32_t ess_t;                // ESS threshold numerator over 2^16 (0: resample every round)
+    uint32_t pad_;
     const ModelDev* model;
     RunCtl* ctl;
     ParticleBuf buf[2];            // buf[r & 1] is written by the propagation of round r
@@ -48,6 +51,7 @@ struct RunDev {
     uint32_t* part_steps;          // per propagation tile: block steps
     double* part_q;                // per reduction tile: sum of grid units
     double* part_e;                // per reduction tile: sum of exp(lw - M)
+    unsigned long long* part_q2;   // per reduction tile: sum of squared grid units (lo, hi), ESS rule only
     double* prefix;                // per reduction tile: grid units before the tile (fold-kernel path)
 };
 

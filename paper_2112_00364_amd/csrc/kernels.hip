@@ -60,6 +60,30 @@ __device__ inline U128 mul128(unsigned long long a, unsigned long long b)
     return U128{__umul64hi(a, b), a * b};
 }
 __device__ inline bool less128(U128 a, U128 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+__device__ inline U128 add128(U128 a, U128 b)
+{
+    const unsigned long long lo = a.lo + b.lo;
+    return U128{a.hi + b.hi + (lo < a.lo ? 1ull : 0ull), lo};
+}
+
+// ESS-triggered resampling (adaptive resampling is listed among RootPPL's
+// features in Sec. 3.3; the rule is this library's reading). With q the
+// quantised weights of the resampling step, ESS = (sum q)^2 / sum q^2, and the
+// round resamples iff ESS < t N / 2^16, decided exactly:
+//   2^16 (sum q)^2 < t N sum q^2.
+// sum q <= N 2^G <= 2^53 and sum q^2 <= 2^G sum q <= 2^85, so with t <= 2^16
+// and N <= 2^24 both sides stay below 2^126. t = 0 always resamples.
+__device__ inline bool ess_says_resample(uint32_t t, uint32_t N, double qtot, U128 q2)
+{
+    if (t == 0) return true;
+    const unsigned long long s1 = (unsigned long long)qtot;
+    const U128 sq = mul128(s1, s1);
+    const U128 lhs{(sq.hi << 16) | (sq.lo >> 48), sq.lo << 16};
+    const unsigned long long k = (unsigned long long)t * N;  // <= 2^40
+    const U128 lo_part = mul128(q2.lo, k);
+    const U128 rhs{lo_part.hi + q2.hi * k, lo_part.lo};
+    return less128(lhs, rhs);
+}
 
 // Number of output slots j in [0, N) whose systematic position lies below
 // cumulative mass W (grid units): #{ j : (j 2^32 + U) Qtot < N W 2^32 }, i.e.
@@ -145,6 +169,12 @@ struct OpMaxU64 {
     static __device__ inline unsigned long long mv(unsigned long long v) { return dpp_u64<C, M>(v); }
 };
 
+struct OpAddU128 {
+    static __device__ inline U128 op(U128 a, U128 b) { return add128(a, b); }
+    template <int C, int M>
+    static __device__ inline U128 mv(U128 v) { return U128{dpp_u64<C, M>(v.hi), dpp_u64<C, M>(v.lo)}; }
+};
+
 template <class Op, class T>
 __device__ inline T wave_incl_scan(T v)
 {
@@ -173,6 +203,11 @@ __device__ inline uint32_t wave_sum(uint32_t v) { return lane63_u32(wave_incl_sc
 __device__ inline unsigned long long wave_max_u64(unsigned long long v)
 {
     return lane63_u64(wave_incl_scan<OpMaxU64>(v));
+}
+__device__ inline U128 wave_sum(U128 v)
+{
+    v = wave_incl_scan<OpAddU128>(v);
+    return U128{lane63_u64(v.hi), lane63_u64(v.lo)};
 }
 
 // Key stored for a tile that produced a NaN or +inf log-weight: above every
@@ -314,13 +349,13 @@ constexpr int kDeepStackBytes = kMaxDepthCap * sizeof(CrbdFrame);
 // Returns false (storing nothing) when a register stack overflowed.
 template <int Kind, class Real, bool kDeep>
 __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint64_t seed, uint32_t j, uint32_t round,
-                                    uint32_t ancestor, uint8_t& blk, double& lw, uint32_t& steps, void* lds_stack)
+                                    uint32_t src, double lw0, uint8_t& blk, double& lw, uint32_t& steps,
+                                    void* lds_stack)
 {
     const ParticleBuf& out = R.buf[round & 1u];
     const ParticleBuf& in = R.buf[(round & 1u) ^ 1u];
-    const uint32_t src = round > 0 ? ancestor : j;
     blk = round > 0 ? in.blk[src] : 0;
-    lw = 0.0;
+    lw = lw0;
     steps = 0;
     Stream s;
     s.start(seed, j, round, kTagPropagate);
@@ -405,10 +440,16 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
     const int32_t status = uniform_i32(ctl->status);
     const uint32_t round = uniform_u32(ctl->round);
     const uint64_t seed = uniform_u64(ctl->seed);
+    const bool carry = uniform_u32(ctl->carry) != 0;
     // The ancestor index is loaded before the control block is consumed, so
     // the two loads overlap (at round 0 the value is not used).
     const uint32_t ancestor = valid ? R.anc[j] : 0u;
     if (status != 0) return;  // uniform over the work-group
+    // After a round that kept its weights (ESS rule) the particle continues in
+    // its own slot from its carried log-weight; otherwise it starts from its
+    // ancestor with weight 0.
+    const uint32_t src = (round > 0 && !carry) ? ancestor : j;
+    const double lw0 = (carry && valid) ? R.lw[j] : 0.0;
     __shared__ uint32_t s_arrived;
     if (threadIdx.x == 0) s_arrived = 0;
     __syncthreads();
@@ -417,7 +458,7 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
     double lw = 0.0;
     uint32_t steps = 0;
     bool deep = false;
-    if (valid) deep = !run_particle<Kind, Real, false>(R, m, seed, j, round, ancestor, blk, lw, steps, nullptr);
+    if (valid) deep = !run_particle<Kind, Real, false>(R, m, seed, j, round, src, lw0, blk, lw, steps, nullptr);
     if constexpr (Kind == 2) {
         __shared__ __align__(16) unsigned char s_stack[kPropThreads / 64][kDeepStackBytes];
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -425,7 +466,7 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
         while (pending) {
             const int leader = __ffsll((long long)pending) - 1;
             if (lane == leader)
-                run_particle<Kind, Real, true>(R, m, seed, j, round, ancestor, blk, lw, steps, s_stack[wave]);
+                run_particle<Kind, Real, true>(R, m, seed, j, round, src, lw0, blk, lw, steps, s_stack[wave]);
             pending &= pending - 1;
         }
     }
@@ -500,32 +541,45 @@ __device__ __forceinline__ void reduce_body(const RunDev& R, const TileRef tr)
     const double M = key_value(key);
     if (key == kBadKey || key == 0 || M == -__builtin_huge_val()) return;  // uniform over the work-group
     const double scale = (double)(1ull << grid_bits(R.n));
+    const bool ess = R.ess_t != 0;  // uniform
     double sq = 0.0, se = 0.0;
+    U128 sq2{0ull, 0ull};
 #pragma unroll
     for (int k = 0; k < kRedItems; ++k) {
         if (base + k < R.n) {
             const double e = fn::exp(x[k] - M);
+            const double q = __builtin_rint(e * scale);
             se += e;
-            sq += __builtin_rint(e * scale);
+            sq += q;
+            if (ess) sq2 = add128(sq2, mul128((unsigned long long)q, (unsigned long long)q));
         }
     }
     sq = wave_sum(sq);
     se = wave_sum(se);
+    if (ess) sq2 = wave_sum(sq2);
     __shared__ double s_q[kRedThreads / 64], s_e[kRedThreads / 64];
+    __shared__ U128 s_q2[kRedThreads / 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) {
         s_q[wave] = sq;
         s_e[wave] = se;
+        s_q2[wave] = sq2;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double q = s_q[0], e = s_e[0];
+        U128 q2 = s_q2[0];
         for (int w = 1; w < kRedThreads / 64; ++w) {
             q += s_q[w];
             e += s_e[w];
+            q2 = add128(q2, s_q2[w]);
         }
         R.part_q[tr.tile] = q;
         R.part_e[tr.tile] = e;
+        if (ess) {
+            R.part_q2[2 * tr.tile] = q2.lo;
+            R.part_q2[2 * tr.tile + 1] = q2.hi;
+        }
     }
 }
 
@@ -541,19 +595,29 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(const RunDev* __restrict
     reduce_body(runs[tr.run], tr);
 }
 
-// log Z update, termination and the next round (one writer per run).
+// log Z update, termination and the next round (one writer per run). active:
+// some particle is not at b_stop; resample: the round resamples (always when
+// active without an ESS threshold). A round that keeps its weights leaves
+// log Z alone and marks the carry for the next propagation.
 __device__ inline void finish_round(const RunDev& R, RunCtl* ctl, bool bad, bool usable, double M, double S,
-                                    bool resampled)
+                                    bool active, bool resample)
 {
     if (bad) {
         ctl->status = -5;  // SMC_ERR_NAN
     } else if (!usable) {
         ctl->log_z = -__builtin_huge_val();
         ctl->status = -6;  // SMC_DEGENERATE
-    } else {
+    } else if (!active) {
         ctl->log_z = ctl->log_z + ((M + fn::log(S)) - fn::log((double)R.n));
-        if (resampled) ctl->round = ctl->round + 1;
-        else ctl->status = 1;  // SMC_FINISHED
+        ctl->status = 1;  // SMC_FINISHED
+    } else if (resample) {
+        ctl->log_z = ctl->log_z + ((M + fn::log(S)) - fn::log((double)R.n));
+        ctl->round = ctl->round + 1;
+        ctl->carry = 0;
+        ctl->resamples = ctl->resamples + 1;
+    } else {
+        ctl->round = ctl->round + 1;
+        ctl->carry = 1;
     }
 }
 
@@ -580,25 +644,37 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __rest
     const uint32_t per = (T + kFoldThreads - 1) / kFoldThreads;
     const uint32_t t0 = threadIdx.x * per;
     const uint32_t t1 = t0 + per < T ? t0 + per : T;
+    const bool ess = R.ess_t != 0;
     double q_local = 0.0, e_local = 0.0;
+    U128 q2_local{0ull, 0ull};
     if (usable)
         for (uint32_t t = t0; t < t1; ++t) {
             q_local += R.part_q[t];
             e_local += R.part_e[t];
+            if (ess) q2_local = add128(q2_local, U128{R.part_q2[2 * t + 1], R.part_q2[2 * t]});
         }
     const double q_incl = wave_incl_scan<OpAddF64>(q_local);  // exact: integer-valued
     const double e_wave = wave_sum(e_local);
+    const U128 q2_wave = ess ? wave_sum(q2_local) : U128{0ull, 0ull};
     __shared__ double s_qw[kFoldThreads / 64], s_ew[kFoldThreads / 64];
+    __shared__ U128 s_q2w[kFoldThreads / 64];
     if (lane == 63) s_qw[wave] = q_incl;
-    if (lane == 0) s_ew[wave] = e_wave;
+    if (lane == 0) {
+        s_ew[wave] = e_wave;
+        s_q2w[wave] = q2_wave;
+    }
     __syncthreads();
     double q_before = 0.0, q_all = 0.0, e_all = 0.0;
+    U128 q2_all{0ull, 0ull};
     for (int w = 0; w < kFoldThreads / 64; ++w) {
         if (w < wave) q_before += s_qw[w];
         q_all += s_qw[w];
         e_all += s_ew[w];
+        q2_all = add128(q2_all, s_q2w[w]);
     }
-    if (usable) {
+    const bool active = ctl->active != 0;
+    const bool resample = active && ess_says_resample(R.ess_t, R.n, q_all, q2_all);
+    if (usable && resample) {
         double run = q_before + (q_incl - q_local);
         for (uint32_t t = t0; t < t1; ++t) {
             R.prefix[t] = run;
@@ -608,7 +684,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __rest
     if (threadIdx.x == 0) {
         ctl->m_cur = M;
         ctl->qtot = q_all;
-        finish_round(R, ctl, bad, usable, M, e_all, ctl->active != 0);
+        finish_round(R, ctl, bad, usable, M, e_all, active, resample);
     }
 }
 
@@ -625,9 +701,11 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     const int32_t status = uniform_i32(ctl->status);
     const unsigned long long key = uniform_u64(ctl->maxkey);
     const bool bad = uniform_u32(ctl->bad) != 0;
-    const bool resample = uniform_u32(ctl->active) != 0;
+    const bool active = uniform_u32(ctl->active) != 0;
+    const bool carry = uniform_u32(ctl->carry) != 0;  // large runs: the fold kernel's decision
     const uint32_t U = uniform_u32(ctl->u);
     const uint32_t N = R.n;
+    const bool ess = R.ess_t != 0;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     __shared__ double s_wave[kRedThreads / 64];
     __shared__ double s_wave2[kRedThreads / 64];
@@ -643,6 +721,7 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     for (int k = 0; k < kRedItems; ++k) x[k] = first + k < N ? R.lw[first + k] : 0.0;
     constexpr int kPer = (int)(kMaxFusedPropTiles * kPropThreads / kTileRed / kRedThreads);
     double qv[kPer], ev[kPer];
+    U128 q2v[kPer];
     if (R.fused) {
         const uint32_t T = R.red_tiles;
 #pragma unroll
@@ -650,6 +729,7 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
             const uint32_t t = threadIdx.x + (uint32_t)i * kRedThreads;
             qv[i] = t < T ? R.part_q[t] : 0.0;
             ev[i] = (tr.tile == 0 && t < T) ? R.part_e[t] : 0.0;
+            q2v[i] = (ess && t < T) ? U128{R.part_q2[2 * t + 1], R.part_q2[2 * t]} : U128{0ull, 0ull};
         }
     }
 
@@ -658,6 +738,7 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     const bool usable = !bad && key != 0 && M != -__builtin_huge_val();
 
     double base = 0.0, Qtot = 0.0;
+    bool resample = active;
     if (R.fused) {
         // every work-group folds the run's tile sums: total mass and own offset
         // (the sums are meaningless when the round is not usable)
@@ -689,11 +770,25 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
             base += s_wave2[w];
             S += s_wave3[w];
         }
-        if (tr.tile == 0 && threadIdx.x == 0) finish_round(R, ctl, bad, usable, M, S, resample);
+        if (ess && usable && active) {
+            // every work-group reaches the same (exact) decision
+            U128 q2{0ull, 0ull};
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) q2 = add128(q2, q2v[i]);
+            q2 = wave_sum(q2);
+            __shared__ U128 s_q2[kRedThreads / 64];
+            if (lane == 0) s_q2[wave] = q2;
+            __syncthreads();
+            U128 Q2{0ull, 0ull};
+            for (int w = 0; w < kRedThreads / 64; ++w) Q2 = add128(Q2, s_q2[w]);
+            resample = ess_says_resample(R.ess_t, N, Qtot, Q2);
+        }
+        if (tr.tile == 0 && threadIdx.x == 0) finish_round(R, ctl, bad, usable, M, S, active, resample);
         __syncthreads();  // s_wave is reused below
     } else {
         Qtot = ctl->qtot;
         base = usable ? R.prefix[tr.tile] : 0.0;
+        resample = active && !carry;
     }
     if (!usable || !resample) return;  // uniform over the work-group
 
@@ -860,6 +955,8 @@ __global__ void k_reset(RunDev* run, uint64_t seed)
     c->status = 0;
     c->active = 0;
     c->bad = 0;
+    c->carry = 0;
+    c->resamples = 0;
 }
 
 // Derived model constants, computed with the pinned device functions so that

@@ -44,13 +44,13 @@ class _Desc(C.Structure):
         ("kind", C.c_int32), ("precision", C.c_int32), ("checkpoint", C.c_int32), ("n_nodes", C.c_int32),
         ("parent", C.POINTER(C.c_int32)), ("left", C.POINTER(C.c_int32)), ("right", C.POINTER(C.c_int32)),
         ("age", C.POINTER(C.c_double)), ("T", C.c_int32), ("y", C.POINTER(C.c_double)),
-        ("params", C.c_double * 16),
+        ("params", C.c_double * 16), ("ess_threshold", C.c_double),
     ]
 
 
 class _Stats(C.Structure):
     _fields_ = [("round", C.c_uint32), ("status", C.c_int32), ("block_steps", C.c_uint64),
-                ("log_z", C.c_double), ("stack_depth", C.c_int32)]
+                ("log_z", C.c_double), ("stack_depth", C.c_int32), ("resamples", C.c_uint32)]
 
 
 class _KernelTimes(C.Structure):
@@ -217,6 +217,7 @@ class Model:
             d.y = y.ctypes.data_as(C.POINTER(C.c_double))
         for i, v in enumerate(spec.get("params", [])):
             d.params[i] = float(v)
+        d.ess_threshold = float(spec.get("ess_threshold", 0.0))
         h = C.c_void_p()
         _check(L.smc_model_register(ctx._h, C.byref(d), C.byref(h)))
         self._h = h
@@ -267,7 +268,7 @@ class Run:
         s = _Stats()
         _check(lib().smc_run_stats(self._h, C.byref(s)))
         return {"round": s.round, "status": s.status, "block_steps": s.block_steps, "log_z": s.log_z,
-                "stack_depth": s.stack_depth}
+                "stack_depth": s.stack_depth, "resamples": s.resamples}
 
     def profile(self, enable: bool = True):
         _check(lib().smc_profile(self._h, 1 if enable else 0))

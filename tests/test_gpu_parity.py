@@ -215,6 +215,7 @@ def run_lockstep(smc, oracle, ctx, spec, n, seed, check_every=1, max_rounds=10**
             if rnd % check_every == 0:
                 assert np.array_equal(gpu.anc(), ref.anc()), f"ancestors round {rnd}"
                 _compare_fields(smc, gpu, ref, spec)  # gathered state
+                assert gpu.stats()["resamples"] == ref.resamples, f"resampling decisions round {rnd}"
             rnd += 1
         lz, lz_ref = gpu.log_z(), ref.log_z
         if math.isfinite(lz_ref):
