@@ -12,7 +12,8 @@ kernel's achieved bandwidth against MI355X's HBM peak, and the CPU oracle's
 throughput on a bounded sample of the same workload. Beside the headline: the
 same workload at 2^24 particles (buffers beyond the Infinity Cache), 512
 batched ClaDS runs of 4096 particles, and a serving stream (one-at-a-time vs
-continuous batching, p50/p99 latency).
+continuous batching, p50/p99 latency), and the headline workload with
+ESS-triggered resampling.
 """
 from __future__ import annotations
 
@@ -142,6 +143,32 @@ def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers):
     return out
 
 
+def ess_point(smc, ctx, spec, n: int, tau: float = 0.5, runs: int = 3):
+    """The headline workload with ESS-triggered resampling (threshold tau):
+    rounds whose effective sample size stays above tau N keep their weights
+    and skip the ancestor pass."""
+    import torch
+    model = smc.Model(ctx, dict(spec, ess_threshold=tau))
+    run = smc.Run(model, n, 91)
+    run.run_to_end()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    for i in range(runs):
+        run.reset(92 + i)
+        assert run.run_to_end() == smc.FINISHED
+    end.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / runs
+    s = run.stats()
+    run.close()
+    model.close()
+    return {"ess_threshold": tau, "particles": n, "runs": runs, "ms_per_run": ms,
+            "rounds": s["round"] + 1, "resampled_rounds": s["resamples"],
+            "block_steps_per_s": s["block_steps"] / (ms / 1e3), "log_z_last": s["log_z"]}
+
+
 def large_point(smc, model, n: int, runs: int = 2):
     """Complete runs at a particle count whose buffers exceed the 256 MB
     Infinity Cache, so every round streams from HBM."""
@@ -180,6 +207,7 @@ def main():
     ap.add_argument("--serving-rates", default="0.9",
                     help="arrival rates as multiples of the one-at-a-time service rate, comma-separated")
     ap.add_argument("--no-large", action="store_true", help="skip the 2^24-particle point")
+    ap.add_argument("--no-ess", action="store_true", help="skip the ESS-triggered point")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -298,6 +326,9 @@ def main():
         "wall_s_timed": wall,
         "log_z": log_zs,
     }
+    if not args.no_ess:
+        print("ESS-triggered point", file=sys.stderr, flush=True)
+        out["ess"] = ess_point(smc, ctx, spec, N_PARTICLES)
     if not args.no_large:
         print("2^24-particle point", file=sys.stderr, flush=True)
         out["large"] = large_point(smc, model, 1 << 24)
