@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11",
           "-Wall", "-Wextra"]
 
-KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3}
+KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3, "seir": 4}
 STOP = 255
 OK, FINISHED, ERR_INVALID, ERR_NAN, DEGENERATE = 0, 1, -1, -5, -6
 READ_BLK, READ_LW, READ_ANC, READ_FIELD0 = 0, 1, 2, 16
@@ -65,6 +65,9 @@ def lib():
     L.or_uniform_from_word.argtypes = [C.c_uint32]; L.or_uniform_from_word.restype = C.c_double
     L.or_poisson_words.argtypes = [C.c_double, u32p, C.c_int32, C.POINTER(C.c_int32)]
     L.or_poisson_words.restype = C.c_int64
+    L.or_log_factorial.argtypes = [C.c_int64]; L.or_log_factorial.restype = C.c_double
+    L.or_log_binomial_pmf.argtypes = [C.c_int64, C.c_int64, C.c_double]; L.or_log_binomial_pmf.restype = C.c_double
+    L.or_sample.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_uint64, C.c_int64, f64p]
     L.or_ancestors.argtypes = [u64p, C.c_uint64, C.c_uint32, u32p]
     L.or_systematic.argtypes = [f64p, C.c_uint64, C.c_uint64, C.c_uint32, u32p, f64p, u64p]
     L.or_systematic.restype = C.c_int32
@@ -145,6 +148,22 @@ def systematic(lw, seed, rnd):
     return int(st), anc, inc.value, int(qtot.value)
 
 
+def log_factorial(k):
+    return lib().or_log_factorial(int(k))
+
+
+def log_binomial_pmf(y, z, p):
+    return lib().or_log_binomial_pmf(int(y), int(z), float(p))
+
+
+def sample(kind, a, b, seed, count):
+    """count draws from one stream: kind "binomial" (n=a, p=b), "gamma" (shape a), "beta" (a, b)."""
+    out = np.zeros(int(count), dtype=np.float64)
+    code = {"binomial": 0, "gamma": 1, "beta": 2}[kind]
+    lib().or_sample(code, float(a), float(b), int(seed), int(count), _ptr(out, C.c_double))
+    return out
+
+
 def ess_resamples(lw, threshold):
     """The ESS rule on one log-weight vector: 1 resample, 0 carry, -1 invalid threshold."""
     lw = np.ascontiguousarray(lw, dtype=np.float64)
@@ -180,8 +199,8 @@ def _model_struct(spec, keep):
     return m
 
 
-N_REAL = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4}
-N_INT = {"geometric": 1, "lgssm": 1, "crbd": 1, "clads": 2}
+N_REAL = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4, "seir": 6}
+N_INT = {"geometric": 1, "lgssm": 1, "crbd": 1, "clads": 2, "seir": 10}
 
 
 def propagate_particle(spec, seed, slot, rnd, blk, reals, ints, stack=None, stack_depth=0):

@@ -288,9 +288,151 @@ static double lognormal(stream* s, double mu_ln, double sigma)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Samplers for the vector-borne disease model (Appendix listing). The paper  */
+/* names the distributions (Beta, Binomial, Poisson, Uniform) but not the     */
+/* algorithms; the readings:                                                  */
+/*  - log k! (or_log_factorial): the sum of log i for k < 16, else the        */
+/*    Stirling series in x = k + 1 up to the x^-7 term;                       */
+/*  - Gamma(a, 1), a >= 1: Marsaglia and Tsang (2000) without the squeeze:    */
+/*    d = a - 1/3, c = 1/sqrt(9d); draw z ~ N(0,1) (Box-Muller as above),     */
+/*    v = (1 + c z)^3, rejected if 1 + c z <= 0, else u ~ U(0,1) and accept   */
+/*    d v iff log u < z^2/2 + d - d v + d log v;                              */
+/*  - Beta(a, b) = X / (X + Y), X ~ Gamma(a), Y ~ Gamma(b);                   */
+/*  - Binomial(n, p): 0 when n = 0 or p = 0 (no draw), n when p = 1; for      */
+/*    p > 1/2 it is n - Binomial(n, 1 - p); with m = n p < 10, inversion by   */
+/*    sequential search from k = 0 (one uniform); otherwise Hoermann's (1993) */
+/*    transformed rejection with squeeze, BTRS (two uniforms per try).        */
+/* Rejection loops stop after OR_MAX_TRIES tries (probability below 1e-100)  */
+/* and then return the last candidate's fallback stated at each sampler.     */
+/* ------------------------------------------------------------------------- */
+#define OR_MAX_TRIES 256
+
+double or_log_factorial(int64_t k)
+{
+    if (k < 2) return 0.0;
+    if (k < 16) {
+        double s = 0.0;
+        for (int64_t i = 2; i <= k; ++i) s = s + or_log((double)i);
+        return s;
+    }
+    double x = (double)(k + 1);
+    double x2 = x * x;
+    double series = (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0 - 1.0 / (1680.0 * x2)) / x2) / x2) / x;
+    return ((x - 0.5) * or_log(x) - x) + (0.5 * or_log(OR_TWO_PI) + series);
+}
+
+/* log k! - [(k + 1/2) log(k + 1) - (k + 1) + log(2 pi) / 2]: the tail of
+ * Stirling's formula used by BTRS. */
+static double stirling_tail(int64_t k)
+{
+    double x = (double)(k + 1);
+    return or_log_factorial(k) - (((double)k + 0.5) * or_log(x) - x + 0.5 * or_log(OR_TWO_PI));
+}
+
+static double gamma_mt(stream* s, double a)
+{
+    double d = a - 1.0 / 3.0;
+    double c = 1.0 / sqrt(9.0 * d);
+    for (int it = 0; it < OR_MAX_TRIES; ++it) {
+        double z = normal01(s);
+        double w = 1.0 + c * z;
+        if (w <= 0.0) continue;
+        double v = w * w * w;
+        double u = next_uniform(s);
+        if (or_log(u) < 0.5 * z * z + d - d * v + d * or_log(v)) return d * v;
+    }
+    return d; /* fallback: the mode (never reached in practice) */
+}
+
+static double beta_draw(stream* s, double a, double b)
+{
+    double x = gamma_mt(s, a);
+    double y = gamma_mt(s, b);
+    return x / (x + y);
+}
+
+static int64_t binomial_small(stream* s, int64_t n, double p)
+{
+    double q = 1.0 - p;
+    double pk = or_exp((double)n * or_log(q));
+    double ratio = p / q;
+    double u = next_uniform(s);
+    int64_t k = 0;
+    while (u > pk && k < n) {
+        u = u - pk;
+        k += 1;
+        pk = pk * ((double)(n - k + 1) / (double)k * ratio);
+    }
+    return k;
+}
+
+static int64_t binomial_btrs(stream* s, int64_t n, double p)
+{
+    double q = 1.0 - p;
+    double spq = sqrt((double)n * p * q);
+    double b = 1.15 + 2.53 * spq;
+    double a = -0.0873 + 0.0248 * b + 0.01 * p;
+    double c = (double)n * p + 0.5;
+    double v_r = 0.92 - 4.2 / b;
+    double r = p / q;
+    double alpha = (2.83 + 5.1 / b) * spq;
+    int64_t m = (int64_t)floor((double)(n + 1) * p);
+    double h = ((double)m + 0.5) * or_log(((double)m + 1.0) / (r * (double)(n - m + 1))) +
+               (stirling_tail(m) + stirling_tail(n - m));
+    int64_t k = (int64_t)floor(c);
+    for (int it = 0; it < OR_MAX_TRIES; ++it) {
+        double u = next_uniform(s) - 0.5;
+        double v = next_uniform(s);
+        double us = 0.5 - fabs(u);
+        double kf = floor((2.0 * a / us + b) * u + c);
+        if (us >= 0.07 && v <= v_r) return (int64_t)kf;
+        if (kf < 0.0 || kf > (double)n) continue;
+        k = (int64_t)kf;
+        double lv = or_log(v * alpha / (a / (us * us) + b));
+        double bound = h + ((double)(n + 1) * or_log((double)(n - m + 1) / (double)(n - k + 1)) +
+                            ((double)k + 0.5) * or_log(r * (double)(n - k + 1) / ((double)k + 1.0))) -
+                       (stirling_tail(k) + stirling_tail(n - k));
+        if (lv <= bound) return k;
+    }
+    return (int64_t)floor(c); /* fallback: the mean, rounded (never reached in practice) */
+}
+
+static int64_t binomial_draw(stream* s, int64_t n, double p)
+{
+    if (n <= 0 || !(p > 0.0)) return 0;
+    if (p >= 1.0) return n;
+    if (p > 0.5) return n - binomial_draw(s, n, 1.0 - p);
+    if ((double)n * p < 10.0) return binomial_small(s, n, p);
+    return binomial_btrs(s, n, p);
+}
+
+/* log of the Binomial(z, p) probability of y, with 0 log 0 = 0. */
+double or_log_binomial_pmf(int64_t y, int64_t z, double p)
+{
+    if (y < 0 || y > z) return -INFINITY;
+    double lw = or_log_factorial(z) - (or_log_factorial(y) + or_log_factorial(z - y));
+    if (y > 0) lw = lw + (double)y * or_log(p);
+    if (z - y > 0) lw = lw + (double)(z - y) * or_log(1.0 - p);
+    return lw;
+}
+
+/* Sampler checks: `count` draws in sequence from the stream of (seed,
+ * particle 0, round 0, tag 0). kind 0: Binomial(n = a, p = b); 1: Gamma(a);
+ * 2: Beta(a, b). Results as doubles. */
+void or_sample(int32_t kind, double a, double b, uint64_t seed, int64_t count, double* out)
+{
+    stream s = {seed, 0, 0, OR_TAG_PROPAGATE, 0};
+    for (int64_t i = 0; i < count; ++i) {
+        if (kind == 0) out[i] = (double)binomial_draw(&s, (int64_t)a, b);
+        else if (kind == 1) out[i] = gamma_mt(&s, a);
+        else out[i] = beta_draw(&s, a, b);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
 /* Particle storage (one array per field, as the paper lays particles out).  */
 /* ------------------------------------------------------------------------- */
-#define OR_MAX_FIELDS 8
+#define OR_MAX_FIELDS 12
 
 struct or_run {
     or_model m;
@@ -310,7 +452,7 @@ struct or_run {
     uint32_t ess_t;            /* ESS threshold numerator over 2^16 (0: always resample) */
     uint32_t resamples;        /* rounds that resampled */
     /* derived constants, computed once from the model parameters */
-    double ln2, log_rho, corr, log_w, obs_c, obs_var;
+    double ln2, log_rho, corr, log_w, obs_c, obs_var, ln10;
     int tips;
 };
 
@@ -562,12 +704,119 @@ static int clads_block(or_run* r, uint64_t i, int b, stream* s, int* ckpt)
 /* ------------------------------------------------------------------------- */
 /* sim: one block execution (Sec. 3.1). Returns the successor block.         */
 /* ------------------------------------------------------------------------- */
+/* ------------------------------------------------------------------------- */
+/* Vector-borne disease (SEIR) model of the Appendix listing: humans and     */
+/* mosquitoes, susceptible / exposed / infectious / recovered counts per     */
+/* day, new human cases observed as Binomial(z, rho) where z counts the      */
+/* new infectious humans since the last observation. Parameters:             */
+/* p = {n humans, fixed hLambda, hDelta, hGamma, mLambda, mDelta, rho (each  */
+/* >= 0 fixes it, < 0 draws it from its Beta prior), fixed initial hE (>= 0),*/
+/* hI (>= 0), hR (>= 0), mS (>= 0)}. Observations y[T] (-1 = missing); the   */
+/* init block conditions on y_0 and day t = 1 .. T-1 on y_t (the listing's   */
+/* recursion bound would read one observation past the end; this is the     */
+/* reading). Fields: real0..5 = hLambda, hDelta, hGamma, mLambda, mDelta,    */
+/* rho; int0..9 = hS, hE, hI, hR, mS, mE, mI, mR, z, t.                      */
+/* ------------------------------------------------------------------------- */
+static double seir_param(stream* s, double fixed, double a, double b)
+{
+    return fixed >= 0.0 ? fixed : beta_draw(s, a, b);
+}
+
+/* condition t: z accumulates new infectious humans; an observed day adds the
+ * Binomial(z, rho) log-probability of y_t and restarts z. */
+static void seir_condition(or_run* r, uint64_t i, int t, int64_t new_infectious)
+{
+    int64_t z = (int64_t)r->ints[8][i] + new_infectious;
+    int64_t y = (int64_t)r->m.y[t];
+    if (y != -1) {
+        r->lw[i] = r->lw[i] + or_log_binomial_pmf(y, z, r->real[5][i]);
+        z = 0;
+    }
+    r->ints[8][i] = (int32_t)z;
+}
+
+static int seir_block(or_run* r, uint64_t i, int b, stream* s, int* ckpt)
+{
+    const double* p = r->m.p;
+    const int64_t n = (int64_t)p[0];
+    *ckpt = 1;
+    if (b == 0) {
+        r->real[0][i] = store_p(r, seir_param(s, p[1], 1.0, 1.0));
+        r->real[1][i] = store_p(r, seir_param(s, p[2], 1.0 + 2.0 / 4.4, 3.0 - 2.0 / 4.4));
+        r->real[2][i] = store_p(r, seir_param(s, p[3], 1.0 + 2.0 / 4.5, 3.0 - 2.0 / 4.5));
+        r->real[3][i] = store_p(r, seir_param(s, p[4], 1.0, 1.0));
+        r->real[4][i] = store_p(r, seir_param(s, p[5], 1.0 + 2.0 / 6.5, 3.0 - 2.0 / 6.5));
+        r->real[5][i] = store_p(r, seir_param(s, p[6], 1.0, 1.0));
+        int64_t hI = p[8] >= 0.0 ? (int64_t)p[8] : 1 + poisson(s, 5.0);
+        int64_t hE = p[7] >= 0.0 ? (int64_t)p[7] : poisson(s, 5.0);
+        int64_t hR = p[9] >= 0.0 ? (int64_t)p[9]
+                                 : (int64_t)floor(uniform_ab(s, 0.0, (double)(n - hI - hE + 1)));
+        int64_t mS = p[10] >= 0.0 ? (int64_t)p[10]
+                                  : (int64_t)floor((double)n * or_exp(uniform_ab(s, -1.0, 2.0) * r->ln10));
+        r->ints[0][i] = (int32_t)(n - hE - hI - hR);
+        r->ints[1][i] = (int32_t)hE;
+        r->ints[2][i] = (int32_t)hI;
+        r->ints[3][i] = (int32_t)hR;
+        r->ints[4][i] = (int32_t)mS;
+        r->ints[5][i] = r->ints[6][i] = r->ints[7][i] = 0;
+        r->ints[8][i] = 0;
+        r->ints[9][i] = 0;
+        seir_condition(r, i, 0, hI); /* the initial deltas: hDeltaI = hI */
+        r->ints[9][i] = 1;
+        return r->m.T > 1 ? 1 : (int)OR_STOP;
+    }
+    const int t = r->ints[9][i];
+    const double hLambda = r->real[0][i], hDelta = r->real[1][i], hGamma = r->real[2][i];
+    const double mLambda = r->real[3][i], mDelta = r->real[4][i];
+    const double mNu = 1.0 / 7.0, mMu = 6.0 / 7.0, mGamma = 0.0;
+    int64_t hSP = r->ints[0][i], hEP = r->ints[1][i], hIP = r->ints[2][i], hRP = r->ints[3][i];
+    int64_t mSP = r->ints[4][i], mEP = r->ints[5][i], mIP = r->ints[6][i], mRP = r->ints[7][i];
+    /* humans */
+    int64_t hN = hSP + hEP + hIP + hRP;
+    int64_t hTau = binomial_draw(s, hSP, 1.0 - or_exp(-((double)mIP / (double)hN)));
+    int64_t hDeltaE = binomial_draw(s, hTau, hLambda);
+    int64_t hDeltaI = binomial_draw(s, hEP, hDelta);
+    int64_t hDeltaR = binomial_draw(s, hIP, hGamma);
+    int64_t hS = hSP - hDeltaE;
+    int64_t hE = hEP + hDeltaE - hDeltaI;
+    int64_t hI = hIP + hDeltaI - hDeltaR;
+    int64_t hR = hRP + hDeltaR;
+    /* mosquitoes */
+    int64_t mTau = binomial_draw(s, mSP, 1.0 - or_exp(-((double)hIP / (double)hN)));
+    int64_t mN = mSP + mEP + mIP + mRP;
+    int64_t mDeltaE = binomial_draw(s, mTau, mLambda);
+    int64_t mDeltaI = binomial_draw(s, mEP, mDelta);
+    int64_t mDeltaR = binomial_draw(s, mIP, mGamma);
+    int64_t mS = mSP - mDeltaE;
+    int64_t mE = mEP + mDeltaE - mDeltaI;
+    int64_t mI = mIP + mDeltaI - mDeltaR;
+    int64_t mR = mRP + mDeltaR;
+    mS = binomial_draw(s, mS, mMu);
+    mE = binomial_draw(s, mE, mMu);
+    mI = binomial_draw(s, mI, mMu);
+    mR = binomial_draw(s, mR, mMu);
+    int64_t mDeltaS = binomial_draw(s, mN, mNu);
+    mS = mS + mDeltaS;
+    r->ints[0][i] = (int32_t)hS;
+    r->ints[1][i] = (int32_t)hE;
+    r->ints[2][i] = (int32_t)hI;
+    r->ints[3][i] = (int32_t)hR;
+    r->ints[4][i] = (int32_t)mS;
+    r->ints[5][i] = (int32_t)mE;
+    r->ints[6][i] = (int32_t)mI;
+    r->ints[7][i] = (int32_t)mR;
+    seir_condition(r, i, t, hDeltaI);
+    r->ints[9][i] = t + 1;
+    return t + 1 < r->m.T ? 1 : (int)OR_STOP;
+}
+
 static int sim(or_run* r, uint64_t i, int b, stream* s, int* ckpt)
 {
     switch (r->m.kind) {
     case OR_GEOMETRIC: return geometric_block(r, i, s, ckpt);
     case OR_LGSSM: return lgssm_block(r, i, b, s, ckpt);
     case OR_CRBD: return crbd_block(r, i, b, s, ckpt);
+    case OR_SEIR: return seir_block(r, i, b, s, ckpt);
     default: return clads_block(r, i, b, s, ckpt);
     }
 }
@@ -589,7 +838,8 @@ static int tree_stack_depth(const or_model* m)
 or_run* or_create(const or_model* m, uint64_t n, uint64_t seed)
 {
     if (n == 0 || n > (1ull << 24)) return NULL;
-    if (m->kind < OR_GEOMETRIC || m->kind > OR_CLADS) return NULL;
+    if (m->kind < OR_GEOMETRIC || m->kind > OR_SEIR) return NULL;
+    if (m->kind == OR_SEIR && (m->T < 1 || !m->y || !(m->p[0] >= 1.0 && m->p[0] <= 1e8))) return NULL;
     if (m->precision != 32 && m->precision != 64) return NULL;
     if ((m->kind == OR_CRBD || m->kind == OR_CLADS) && (m->n_nodes < 1 || !m->parent || !m->age || !m->left))
         return NULL;
@@ -605,8 +855,10 @@ or_run* or_create(const or_model* m, uint64_t n, uint64_t seed)
     case OR_GEOMETRIC: r->n_int = 1; break;
     case OR_LGSSM: r->n_real = 1; r->n_int = 1; break;
     case OR_CRBD: r->n_real = 2; r->n_int = 1; break;
+    case OR_SEIR: r->n_real = 6; r->n_int = 10; break;
     default: r->n_real = 4; r->n_int = 2; break;
     }
+    r->ln10 = or_log(10.0);
     r->blk = (uint8_t*)calloc(n, 1);             /* a_n = b0 */
     r->lw = (double*)calloc(n, sizeof(double));  /* log weights 0 */
     r->anc = (uint32_t*)calloc(n, sizeof(uint32_t));

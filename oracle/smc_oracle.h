@@ -29,14 +29,14 @@
 extern "C" {
 #endif
 
-enum { OR_GEOMETRIC = 0, OR_LGSSM = 1, OR_CRBD = 2, OR_CLADS = 3 };
+enum { OR_GEOMETRIC = 0, OR_LGSSM = 1, OR_CRBD = 2, OR_CLADS = 3, OR_SEIR = 4 };
 enum { OR_OK = 0, OR_FINISHED = 1, OR_ERR_INVALID = -1, OR_ERR_NAN = -5, OR_DEGENERATE = -6 };
 enum { OR_TAG_PROPAGATE = 0, OR_TAG_RESAMPLE = 1 };
 #define OR_STOP 255u
 
 /* Model description. Parameters are read per model kind (see smc_oracle.c). */
 typedef struct {
-    int32_t kind;       /* OR_GEOMETRIC .. OR_CLADS */
+    int32_t kind;       /* OR_GEOMETRIC .. OR_SEIR */
     int32_t precision;  /* 32 or 64: storage precision of real-valued particle state */
     int32_t checkpoint; /* geometric only: 1 = checkpoint after each heads, 0 = none */
     int32_t n_nodes;    /* trees: 2*tips-1 nodes in preorder, root = 0 */
@@ -60,6 +60,9 @@ double or_cos2pi(double u);
 uint32_t or_word(uint64_t seed, uint32_t k, uint32_t particle, uint32_t round, uint32_t tag);
 double or_uniform_from_word(uint32_t w);
 int64_t or_poisson_words(double m, const uint32_t* words, int32_t n_words, int32_t* used);
+double or_log_factorial(int64_t k);
+double or_log_binomial_pmf(int64_t y, int64_t z, double p);
+void or_sample(int32_t kind, double a, double b, uint64_t seed, int64_t count, double* out);
 
 /* Resampling alone (Alg. 1 step 3) on a given log-weight vector. */
 void or_ancestors(const uint64_t* Q, uint64_t n, uint32_t U, uint32_t* anc);

@@ -163,6 +163,55 @@ def clads_spec(tree, precision=32, rho=1.0, scale_l0=1.0, eps=(0.0, 1.0), alpha=
                        fixed_alpha, fixed_sigma]}
 
 
+SEIR_HUMANS = 7370
+
+
+def seir_data(T: int, seed: int, n=SEIR_HUMANS, hLambda=0.35, hDelta=0.3, hGamma=0.35, mLambda=0.35,
+              mDelta=0.3, rho=0.6, hE=5, hI=6, hR=0, mS=12000, missing=0.05) -> np.ndarray:
+    """Synthetic daily counts of reported new cases (the vector-borne disease
+    model's observations): one forward simulation of the SEIR dynamics with
+    NumPy's generator at the given parameters; a fraction of days is missing
+    (-1). Input preparation only, independent of the samplers under test."""
+    rng = np.random.default_rng(seed)
+    bi = rng.binomial
+    hS = n - hE - hI - hR
+    mE = mI = mR = 0
+    y = np.empty(T, dtype=np.float64)
+    z = hI
+    for t in range(T):
+        if t > 0:
+            hN = hS + hE + hI + hR
+            hTau = bi(hS, 1.0 - math.exp(-mI / hN))
+            dE = bi(hTau, hLambda)
+            dI = bi(hE, hDelta)
+            dR = bi(hI, hGamma)
+            mTau = bi(mS, 1.0 - math.exp(-hI / hN))
+            mN = mS + mE + mI + mR
+            mdE = bi(mTau, mLambda)
+            mdI = bi(mE, mDelta)
+            hS, hE, hI, hR = hS - dE, hE + dE - dI, hI + dI - dR, hR + dR
+            mS, mE, mI = mS - mdE, mE + mdE - mdI, mI + mdI
+            mS, mE, mI, mR = bi(mS, 6 / 7), bi(mE, 6 / 7), bi(mI, 6 / 7), bi(mR, 6 / 7)
+            mS += bi(mN, 1 / 7)
+            z += dI
+        if rng.random() < missing and t > 0:
+            y[t] = -1.0
+        else:
+            y[t] = float(bi(z, rho))
+            z = 0
+    return y
+
+
+def seir_spec(y, precision=32, n=SEIR_HUMANS, fixed_rates=None, initial=None) -> dict:
+    """Vector-borne disease model (SEIR, Appendix listing). params: n humans,
+    fixed rates (hLambda, hDelta, hGamma, mLambda, mDelta, rho; -1 draws from
+    the Beta priors), fixed initial (hE, hI, hR, mS; -1 draws them)."""
+    rates = list(fixed_rates) if fixed_rates is not None else [-1.0] * 6
+    init = list(initial) if initial is not None else [-1.0] * 4
+    return {"kind": "seir", "precision": precision, "y": np.asarray(y, dtype=np.float64),
+            "params": [float(n)] + [float(v) for v in rates] + [float(v) for v in init]}
+
+
 def request_stream(n_requests: int, seed: int, rate_per_s: float,
                    tips=(16, 512), log2_particles=(10, 18)) -> list[dict]:
     """Serving workload: Poisson arrivals; each request is CRBD or ClaDS (1/2 each)

@@ -121,3 +121,73 @@ def crbd_log_marginal(tree, rho=1.0, scale_lambda=1.0, scale_mu=0.5, n_grid=400)
             ll[i, j] = crbd_log_lik(tree, lam[i], mu[j], rho)
     mx = ll.max()
     return mx + math.log(float((w[:, None] * w[None, :] * np.exp(ll - mx)).sum()))
+
+
+# --- vector-borne disease (SEIR) model: exact evidence for tiny populations -------------
+
+def _binom_pmf(N, p):
+    if N <= 0 or p <= 0.0:
+        return [(0, 1.0)]
+    if p >= 1.0:
+        return [(N, 1.0)]
+    return [(k, math.comb(N, k) * p ** k * (1.0 - p) ** (N - k)) for k in range(N + 1)]
+
+
+def _expand(states, step):
+    """states: {tuple: mass}; step(state) yields (new_state, probability)."""
+    out = {}
+    for s, w in states.items():
+        for s2, q in step(s):
+            if q > 0.0:
+                out[s2] = out.get(s2, 0.0) + w * q
+    return out
+
+
+def seir_exact_log_evidence(y, n, rates, initial):
+    """log P(y_0 .. y_{T-1}) of the vector-borne disease model with fixed rates
+    (hLambda, hDelta, hGamma, mLambda, mDelta, rho) and fixed initial (hE, hI,
+    hR, mS), by the forward algorithm over the joint counts (exact Binomial
+    probabilities, one draw at a time, equal states merged). Only feasible for
+    a handful of individuals."""
+    hL, hD, hG, mL, mD, rho = rates
+    hE0, hI0, hR0, mS0 = initial
+
+    def condition(states, t):
+        if y[t] < 0:
+            return states
+        out = {}
+        for s, w in states.items():
+            z = s[-1]
+            k = int(y[t])
+            if k > z:
+                continue
+            q = math.comb(z, k) * rho ** k * (1.0 - rho) ** (z - k)
+            s2 = s[:-1] + (0,)
+            out[s2] = out.get(s2, 0.0) + w * q
+        return out
+
+    # state: (hS, hE, hI, hR, mS, mE, mI, mR, z)
+    states = condition({(n - hE0 - hI0 - hR0, hE0, hI0, hR0, mS0, 0, 0, 0, hI0): 1.0}, 0)
+    for t in range(1, len(y)):
+        # (previous state, draws so far...) as flat tuples
+        st = {s + (s[0] + s[1] + s[2] + s[3], s[4] + s[5] + s[6] + s[7]): w for s, w in states.items()}
+        # hTau ~ Bin(hS, 1 - exp(-mI/hN)), then dE ~ Bin(hTau, hL)
+        st = _expand(st, lambda s: ((s + (k,), q) for k, q in _binom_pmf(s[0], 1.0 - math.exp(-s[6] / s[9]))))
+        st = _expand(st, lambda s: ((s[:-1] + (k,), q) for k, q in _binom_pmf(s[-1], hL)))       # dE
+        st = _expand(st, lambda s: ((s + (k,), q) for k, q in _binom_pmf(s[1], hD)))             # dI
+        st = _expand(st, lambda s: ((s + (k,), q) for k, q in _binom_pmf(s[2], hG)))             # dR
+        st = _expand(st, lambda s: ((s + (k,), q) for k, q in _binom_pmf(s[4], 1.0 - math.exp(-s[2] / s[9]))))
+        st = _expand(st, lambda s: ((s[:-1] + (k,), q) for k, q in _binom_pmf(s[-1], mL)))       # mdE
+        st = _expand(st, lambda s: ((s + (k,), q) for k, q in _binom_pmf(s[5], mD)))             # mdI
+        # s = (hS, hE, hI, hR, mS, mE, mI, mR, z, hN, mN, dE, dI, dR, mdE, mdI)
+        st = _expand(st, lambda s: [((s[0] - s[11], s[1] + s[11] - s[12], s[2] + s[12] - s[13], s[3] + s[13],
+                                      s[4] - s[14], s[5] + s[14] - s[15], s[6] + s[15], s[7],
+                                      s[8] + s[12], s[10]), 1.0)])
+        # survival of each mosquito class, then births from the previous total
+        for idx in (4, 5, 6, 7):
+            st = _expand(st, lambda s, i=idx: ((s[:i] + (k,) + s[i + 1:], q)
+                                               for k, q in _binom_pmf(s[i], 6.0 / 7.0)))
+        st = _expand(st, lambda s: ((s[:4] + (s[4] + k,) + s[5:9], q) for k, q in _binom_pmf(s[9], 1.0 / 7.0)))
+        states = condition(st, t)
+    total = sum(states.values())
+    return math.log(total) if total > 0 else -math.inf
