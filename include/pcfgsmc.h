@@ -82,7 +82,8 @@ enum {
     SMC_MODEL_GEOMETRIC = 0, /* Sec. 2, Fig. 2: weighted geometric program */
     SMC_MODEL_LGSSM = 1,     /* eq. (2), Fig. 4: linear-Gaussian state-space model */
     SMC_MODEL_CRBD = 2,      /* Appendix B listing: constant-rate birth-death */
-    SMC_MODEL_CLADS = 3      /* birth-death with cladogenetic rate shifts */
+    SMC_MODEL_CLADS = 3,     /* birth-death with cladogenetic rate shifts */
+    SMC_MODEL_SEIR = 4       /* Appendix listing: vector-borne disease (SEIR) */
 };
 
 /* Model description (all pointers are host memory, deep-copied to the device
@@ -100,6 +101,15 @@ enum {
  *   CLADS      {rho, lambda0 scale, eps lo, eps hi, alpha lo, alpha hi,
  *              sigma scale, max events, max depth, fixed lambda0 (>0),
  *              fixed eps (>=0), fixed alpha (>0), fixed sigma (>=0)}.
+ *   SEIR       {humans n in [1, 10^7], fixed hLambda, hDelta, hGamma, mLambda,
+ *              mDelta, rho (each in [0, 1]; < 0 draws it from the listing's
+ *              Beta prior), fixed initial hE, hI, hR, mS (integers; < 0 draws
+ *              them)}; y has T daily counts of reported new cases (-1 =
+ *              missing). The init block conditions on y_0 and each later
+ *              round simulates one day t and conditions on y_t. Fields: six
+ *              rates (storage precision), then int32 hS, hE, hI, hR, mS, mE,
+ *              mI, mR, z (new infectious humans since the last observation)
+ *              and the day.
  * Hidden-event budgets must lie in [0, 10^6] and recursion depths in [1, 32].
  * ess_threshold: 0 resamples every round (Algorithm 1). A value tau in (0, 1]
  *   turns on resampling triggered by the effective sample size (listed among
@@ -242,7 +252,11 @@ smc_status smc_batch_destroy(smc_batch* b); /* NULL-safe */
  * (input = w as a double), 5 Box-Muller normal from the word pair
  * (in[2i], in[2i+1]) -> out[i], 6 Poisson(in[2i]) drawn from the stream of
  * seed in[2i+1] (an integer below 2^53), particle i, round 0, tag 0, from word
- * 0 -> out[i] (-1 when the mean exceeds the event cap). */
+ * 0 -> out[i] (-1 when the mean exceeds the event cap); 7 Binomial(in[3i],
+ * in[3i+1]) and 8 Gamma(in[3i]) (in[3i+1] < 0) or Beta(in[3i], in[3i+1]), each
+ * the first draw of the stream of seed in[3i+2], particle 0, round 0, tag 0;
+ * 9 log k! of k = in[i]; 10 log of the Binomial(in[3i+1], in[3i+2])
+ * probability of in[3i]. */
 smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n);
 /* Philox4x32-10 on n counters: ctr (device, 4 x uint32 each), key (2 x uint32
  * each), out (device, 4 x uint32 each). */

@@ -84,10 +84,21 @@ struct DeviceArena {
     }
 };
 
-int real_fields(int kind) { return kind == SMC_MODEL_LGSSM ? 1 : kind == SMC_MODEL_CRBD ? 2 : kind == SMC_MODEL_CLADS ? 4 : 0; }
-int stored_int_fields(int kind) { return kind == SMC_MODEL_GEOMETRIC ? 1 : 0; }
-// Int fields as the model defines them (some are the round, not stored).
-int logical_int_fields(int kind) { return kind == SMC_MODEL_CLADS ? 2 : 1; }
+int real_fields(int kind)
+{
+    switch (kind) {
+    case SMC_MODEL_LGSSM: return 1;
+    case SMC_MODEL_CRBD: return 2;
+    case SMC_MODEL_CLADS: return 4;
+    case SMC_MODEL_SEIR: return 6;
+    default: return 0;
+    }
+}
+int stored_int_fields(int kind) { return kind == SMC_MODEL_GEOMETRIC ? 1 : kind == SMC_MODEL_SEIR ? 9 : 0; }
+// Int fields as the model defines them (cursor-like ones follow the round and
+// are not stored): geometric flips; LGSSM t; CRBD node; ClaDS node and stack
+// size; SEIR nine counts and the day.
+int logical_int_fields(int kind) { return kind == SMC_MODEL_CLADS ? 2 : kind == SMC_MODEL_SEIR ? 10 : 1; }
 
 }  // namespace
 
@@ -267,7 +278,7 @@ smc_status do_resample(smc_run* r)
 // Rounds a model needs when every particle advances in lockstep (0 = unknown).
 uint32_t lockstep_rounds(const smc_model* m)
 {
-    if (m->kind == SMC_MODEL_LGSSM) return (uint32_t)m->T;
+    if (m->kind == SMC_MODEL_LGSSM || m->kind == SMC_MODEL_SEIR) return (uint32_t)m->T;
     if (m->kind == SMC_MODEL_CRBD || m->kind == SMC_MODEL_CLADS) return (uint32_t)m->n_nodes;
     return 0;
 }
@@ -314,7 +325,7 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
 {
     if (!ctx || !d || !out) return fail(SMC_ERR_INVALID, "NULL argument");
     *out = nullptr;
-    if (d->kind < SMC_MODEL_GEOMETRIC || d->kind > SMC_MODEL_CLADS) return fail(SMC_ERR_INVALID, "unknown model kind");
+    if (d->kind < SMC_MODEL_GEOMETRIC || d->kind > SMC_MODEL_SEIR) return fail(SMC_ERR_INVALID, "unknown model kind");
     if (d->precision != 32 && d->precision != 64) return fail(SMC_ERR_INVALID, "precision must be 32 or 64");
     const bool tree = d->kind == SMC_MODEL_CRBD || d->kind == SMC_MODEL_CLADS;
     if (tree) {
@@ -330,8 +341,21 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
         if (!(d->params[ev] >= 0.0 && d->params[ev] <= 1e6)) return fail(SMC_ERR_INVALID, "max events must be in [0, 10^6]");
         if (!(d->params[0] > 0.0 && d->params[0] <= 1.0)) return fail(SMC_ERR_INVALID, "rho must be in (0, 1]");
     }
-    if (d->kind == SMC_MODEL_LGSSM && (d->T < 1 || d->T > (1 << 24) || !d->y))
+    if ((d->kind == SMC_MODEL_LGSSM || d->kind == SMC_MODEL_SEIR) && (d->T < 1 || d->T > (1 << 24) || !d->y))
         return fail(SMC_ERR_INVALID, "observations missing");
+    if (d->kind == SMC_MODEL_SEIR) {
+        const double* p = d->params;
+        auto count = [](double v) { return v == std::floor(v) && v >= 0.0 && v <= 2147483647.0; };
+        if (!(count(p[0]) && p[0] >= 1.0 && p[0] <= 1e7)) return fail(SMC_ERR_INVALID, "humans must be in [1, 10^7]");
+        for (int i = 1; i <= 6; ++i)
+            if (!(p[i] < 0.0 || p[i] <= 1.0)) return fail(SMC_ERR_INVALID, "fixed rates must lie in [0, 1]");
+        for (int i = 7; i <= 10; ++i)
+            if (!(p[i] < 0.0 || count(p[i]))) return fail(SMC_ERR_INVALID, "fixed initial counts must be integers");
+        if (!(p[7] < 0.0 || p[8] < 0.0 || p[9] < 0.0 || p[7] + p[8] + p[9] <= p[0]))
+            return fail(SMC_ERR_INVALID, "initial humans exceed the population");
+        for (int t = 0; t < d->T; ++t)
+            if (!(d->y[t] == -1.0 || count(d->y[t]))) return fail(SMC_ERR_INVALID, "observations must be counts or -1");
+    }
     if (!(d->ess_threshold >= 0.0 && d->ess_threshold <= 1.0))
         return fail(SMC_ERR_INVALID, "ess_threshold must be in [0, 1]");
     smc_model* m = new (std::nothrow) smc_model();
@@ -342,7 +366,7 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
     m->precision = d->precision;
     m->checkpoint = d->checkpoint;
     m->n_nodes = tree ? d->n_nodes : 0;
-    m->T = d->kind == SMC_MODEL_LGSSM ? d->T : 0;
+    m->T = (d->kind == SMC_MODEL_LGSSM || d->kind == SMC_MODEL_SEIR) ? d->T : 0;
     m->ess_t = (uint32_t)std::nearbyint(d->ess_threshold * 65536.0);
     ModelDev& h = m->host;
     h.kind = d->kind;
@@ -379,7 +403,7 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
             ok = ok && h.sp_before;
         }
     }
-    if (d->kind == SMC_MODEL_LGSSM) {
+    if (d->kind == SMC_MODEL_LGSSM || d->kind == SMC_MODEL_SEIR) {
         h.y = (const double*)upload(d->y, sizeof(double) * d->T);
         ok = ok && h.y;
     }
@@ -594,7 +618,7 @@ smc_status smc_read(smc_run* r, int32_t what, void* dst, size_t bytes)
     f -= nr;
     if (f >= 0 && f < logical_int_fields(m->kind)) {
         if (bytes < n * 4) return fail(SMC_ERR_INVALID, "destination too small");
-        if (m->kind == SMC_MODEL_GEOMETRIC) return fetch(b.ints[0], 4, 1);
+        if (f < stored_int_fields(m->kind)) return fetch(b.ints[f], 4, 1);
         // cursor-like fields advance once per round for every particle
         int32_t v = (int32_t)last_round + 1;
         if (m->kind == SMC_MODEL_CLADS && f == 1) {
@@ -902,7 +926,7 @@ smc_status smc_batch_destroy(smc_batch* b)
 smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n)
 {
     if (!ctx || !in || !out) return fail(SMC_ERR_INVALID, "NULL argument");
-    if (op < 0 || op > 6) return fail(SMC_ERR_INVALID, "unknown op");
+    if (op < 0 || op > 10) return fail(SMC_ERR_INVALID, "unknown op");
     if (n == 0) return SMC_OK;
     HIP_TRY(launch_selftest_math(op, in, out, n, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -266,4 +266,128 @@ __device__ inline int draw_poisson(Stream& s, double m)
     return total;
 }
 
+// ---------------------------------------------------------------------------
+// Samplers of the vector-borne disease model. The paper names the
+// distributions, not the algorithms; the pinned readings:
+//  - log k!: the sum of log i for k < 16, else the Stirling series in
+//    x = k + 1 up to the x^-7 term;
+//  - Gamma(a, 1), a >= 1: Marsaglia and Tsang (2000) without the squeeze;
+//  - Beta(a, b) = X / (X + Y) with X ~ Gamma(a), Y ~ Gamma(b);
+//  - Binomial(n, p): 0 for n = 0 or p = 0 and n for p = 1 (no draw);
+//    n - Binomial(n, 1 - p) for p > 1/2; inversion by sequential search when
+//    n p < 10; otherwise Hoermann's (1993) transformed rejection with squeeze
+//    (BTRS), two uniforms per try.
+// Rejection loops stop after kMaxTries tries (probability below 1e-100) and
+// return the stated fallback.
+// ---------------------------------------------------------------------------
+constexpr int kMaxTries = 256;
+
+__device__ inline double log_factorial(long long k)
+{
+    if (k < 2) return 0.0;
+    if (k < 16) {
+        double s = 0.0;
+        for (long long i = 2; i <= k; ++i) s = s + fn::log((double)i);
+        return s;
+    }
+    const double x = (double)(k + 1);
+    const double x2 = x * x;
+    const double series = (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0 - 1.0 / (1680.0 * x2)) / x2) / x2) / x;
+    return ((x - 0.5) * fn::log(x) - x) + (0.5 * fn::log(fn::kTau) + series);
+}
+
+// log k! - [(k + 1/2) log(k + 1) - (k + 1) + log(2 pi) / 2]
+__device__ inline double stirling_tail(long long k)
+{
+    const double x = (double)(k + 1);
+    return log_factorial(k) - ((((double)k + 0.5) * fn::log(x) - x) + 0.5 * fn::log(fn::kTau));
+}
+
+__device__ inline double draw_gamma(Stream& s, double a)
+{
+    const double d = a - 1.0 / 3.0;
+    const double c = 1.0 / fn::sqrt(9.0 * d);
+    for (int it = 0; it < kMaxTries; ++it) {
+        const double z = draw_normal(s);
+        const double w = 1.0 + c * z;
+        if (w <= 0.0) continue;
+        const double v = w * w * w;
+        const double u = s.uniform();
+        if (fn::log(u) < 0.5 * z * z + d - d * v + d * fn::log(v)) return d * v;
+    }
+    return d;
+}
+
+__device__ inline double draw_beta(Stream& s, double a, double b)
+{
+    const double x = draw_gamma(s, a);
+    const double y = draw_gamma(s, b);
+    return x / (x + y);
+}
+
+__device__ inline long long binomial_small(Stream& s, long long n, double p)
+{
+    const double q = 1.0 - p;
+    double pk = fn::exp((double)n * fn::log(q));
+    const double ratio = p / q;
+    double u = s.uniform();
+    long long k = 0;
+    while (u > pk && k < n) {
+        u = u - pk;
+        k += 1;
+        pk = pk * ((double)(n - k + 1) / (double)k * ratio);
+    }
+    return k;
+}
+
+__device__ inline long long binomial_btrs(Stream& s, long long n, double p)
+{
+    const double q = 1.0 - p;
+    const double spq = fn::sqrt((double)n * p * q);
+    const double b = 1.15 + 2.53 * spq;
+    const double a = -0.0873 + 0.0248 * b + 0.01 * p;
+    const double c = (double)n * p + 0.5;
+    const double v_r = 0.92 - 4.2 / b;
+    const double r = p / q;
+    const double alpha = (2.83 + 5.1 / b) * spq;
+    const long long m = (long long)__builtin_floor((double)(n + 1) * p);
+    const double h = ((double)m + 0.5) * fn::log(((double)m + 1.0) / (r * (double)(n - m + 1))) +
+                     (stirling_tail(m) + stirling_tail(n - m));
+    for (int it = 0; it < kMaxTries; ++it) {
+        const double u = s.uniform() - 0.5;
+        const double v = s.uniform();
+        const double us = 0.5 - __builtin_fabs(u);
+        const double kf = __builtin_floor((2.0 * a / us + b) * u + c);
+        if (us >= 0.07 && v <= v_r) return (long long)kf;
+        if (kf < 0.0 || kf > (double)n) continue;
+        const long long k = (long long)kf;
+        const double lv = fn::log(v * alpha / (a / (us * us) + b));
+        const double bound = h + ((double)(n + 1) * fn::log((double)(n - m + 1) / (double)(n - k + 1)) +
+                                  ((double)k + 0.5) * fn::log(r * (double)(n - k + 1) / ((double)k + 1.0))) -
+                             (stirling_tail(k) + stirling_tail(n - k));
+        if (lv <= bound) return k;
+    }
+    return (long long)__builtin_floor(c);
+}
+
+__device__ inline long long draw_binomial(Stream& s, long long n, double p)
+{
+    if (n <= 0 || !(p > 0.0)) return 0;
+    if (p >= 1.0) return n;
+    const bool flip = p > 0.5;
+    const double pp = flip ? 1.0 - p : p;
+    const long long k = (double)n * pp < 10.0 ? binomial_small(s, n, pp) : binomial_btrs(s, n, pp);
+    return flip ? n - k : k;
+}
+
+// log of the Binomial(z, p) probability of y, with 0 log 0 = 0.
+__device__ inline double log_binomial_pmf(long long y, long long z, double p)
+{
+    if (y < 0 || y > z) return -__builtin_huge_val();
+    double lw = log_factorial(z) - (log_factorial(y) + log_factorial(z - y));
+    if (y > 0) lw = lw + (double)y * fn::log(p);
+    if (z - y > 0) lw = lw + (double)(z - y) * fn::log(1.0 - p);
+    return lw;
+}
+
 }  // namespace pcfg

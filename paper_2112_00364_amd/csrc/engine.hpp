@@ -28,8 +28,8 @@ struct alignas(64) RunCtl {
 // fields, and the ClaDS stack (level-major: level k of particle j at k*n + j).
 struct ParticleBuf {
     uint8_t* blk;
-    void* real[4];
-    int32_t* ints[2];
+    void* real[6];
+    int32_t* ints[9];
     void* stack;
 };
 

@@ -396,6 +396,24 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint64_t
         }
         store_real<Real>(out.real[0], j, st.lambda);
         store_real<Real>(out.real[1], j, st.mu);
+    } else if constexpr (Kind == 4) {
+        typename Seir<Real>::State st{};
+        if (round > 0) {
+#pragma unroll
+            for (int f = 0; f < Seir<Real>::kReal; ++f) st.r[f] = load_real<Real>(in.real[f], src);
+#pragma unroll
+            for (int f = 0; f < Seir<Real>::kInt; ++f) st.c[f] = in.ints[f][src];
+        }
+        while (blk != kStop) {
+            bool ck = false;
+            blk = Seir<Real>::sim(m, round, blk, st, lw, s, ck);
+            steps += 1;
+            if (ck) break;
+        }
+#pragma unroll
+        for (int f = 0; f < Seir<Real>::kReal; ++f) store_real<Real>(out.real[f], j, st.r[f]);
+#pragma unroll
+        for (int f = 0; f < Seir<Real>::kInt; ++f) out.ints[f][j] = (int32_t)st.c[f];
     } else {
         using Stack = ClaDSGlobalFrames;
         const uint64_t levels = (uint64_t)kMaxDepthCap * R.n;
@@ -921,6 +939,20 @@ __global__ void k_selftest_math(int op, const double* __restrict__ in, double* _
         r = (double)draw_poisson(s, in[2 * i]);
         break;
     }
+    case 7: {  // in: (n, p, seed) -> first Binomial(n, p) draw of stream (seed, particle 0)
+        Stream s;
+        s.start((uint64_t)in[3 * i + 2], 0u, 0u, kTagPropagate);
+        r = (double)draw_binomial(s, (long long)in[3 * i], in[3 * i + 1]);
+        break;
+    }
+    case 8: {  // in: (a, b, seed) -> Gamma(a) if b < 0, else Beta(a, b)
+        Stream s;
+        s.start((uint64_t)in[3 * i + 2], 0u, 0u, kTagPropagate);
+        r = in[3 * i + 1] < 0.0 ? draw_gamma(s, in[3 * i]) : draw_beta(s, in[3 * i], in[3 * i + 1]);
+        break;
+    }
+    case 9: r = log_factorial((long long)in[i]); break;
+    case 10: r = log_binomial_pmf((long long)in[3 * i], (long long)in[3 * i + 1], in[3 * i + 2]); break;
     default: r = 0.0;
     }
     out[i] = r;
@@ -970,6 +1002,7 @@ __global__ void k_model_setup(ModelDev* m)
         m->obs_var = m->p[3] * m->p[3];
         m->obs_c = -0.5 * fn::log(fn::kTau * m->obs_var);
     }
+    m->ln10 = fn::log(10.0);
     if (m->kind == 2 || m->kind == 3) {
         const int tips = (m->n_nodes + 1) / 2;
         m->log_rho = fn::log(m->p[0]);
@@ -993,7 +1026,9 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     else if (kind == 2 && precision == 32) hipLaunchKernelGGL((k_propagate<2, float>), g, b, 0, st, runs, tiles);
     else if (kind == 2) hipLaunchKernelGGL((k_propagate<2, double>), g, b, 0, st, runs, tiles);
     else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate<3, float>), g, b, 0, st, runs, tiles);
-    else hipLaunchKernelGGL((k_propagate<3, double>), g, b, 0, st, runs, tiles);
+    else if (kind == 3) hipLaunchKernelGGL((k_propagate<3, double>), g, b, 0, st, runs, tiles);
+    else if (precision == 32) hipLaunchKernelGGL((k_propagate<4, float>), g, b, 0, st, runs, tiles);
+    else hipLaunchKernelGGL((k_propagate<4, double>), g, b, 0, st, runs, tiles);
     return hipGetLastError();
 }
 
@@ -1006,7 +1041,9 @@ hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipS
     else if (kind == 2 && precision == 32) hipLaunchKernelGGL((k_propagate_one<2, float>), g, b, 0, st, run);
     else if (kind == 2) hipLaunchKernelGGL((k_propagate_one<2, double>), g, b, 0, st, run);
     else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate_one<3, float>), g, b, 0, st, run);
-    else hipLaunchKernelGGL((k_propagate_one<3, double>), g, b, 0, st, run);
+    else if (kind == 3) hipLaunchKernelGGL((k_propagate_one<3, double>), g, b, 0, st, run);
+    else if (precision == 32) hipLaunchKernelGGL((k_propagate_one<4, float>), g, b, 0, st, run);
+    else hipLaunchKernelGGL((k_propagate_one<4, double>), g, b, 0, st, run);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ struct ModelDev {
     const int32_t* sp_before;  // ClaDS: pending-stack size when node r is visited
     double p[16];
     // constants derived on the device with the pinned functions
-    double ln2, log_rho, corr, log_w, obs_c, obs_var;
+    double ln2, log_rho, corr, log_w, obs_c, obs_var, ln10;
 };
 
 // ---------------------------------------------------------------------------
@@ -441,6 +441,114 @@ struct Clads {
         }
         lw = w_acc;
         return node + 1 < m.n_nodes ? 1 : kStop;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Vector-borne disease (SEIR) model of the Appendix listing: human and
+// mosquito susceptible / exposed / infectious / recovered counts per day; new
+// human cases are observed as Binomial(z, rho), z counting the humans that
+// became infectious since the last observed day. Block 0 draws the rates
+// (Beta priors, or fixed by the parameters) and the initial counts and
+// conditions on y_0; block 1 simulates day t = round and conditions on y_t;
+// the last day is followed by b_stop. Reals (storage precision): hLambda,
+// hDelta, hGamma, mLambda, mDelta, rho. Counts: hS, hE, hI, hR, mS, mE, mI,
+// mR, z. params = {n humans, six fixed rates (< 0 draws), fixed initial hE,
+// hI, hR, mS (< 0 draws)}.
+// ---------------------------------------------------------------------------
+template <class Real>
+struct Seir {
+    static constexpr int kReal = 6, kInt = 9;
+    struct State {
+        double r[kReal];
+        long long c[kInt];
+    };
+
+    __device__ static inline double rate(Stream& s, double fixed, double a, double b)
+    {
+        return fixed >= 0.0 ? fixed : draw_beta(s, a, b);
+    }
+
+    // the listing's condition: accumulate new infectious humans; an observed
+    // day weighs Binomial(z, rho) at y_t and restarts the count
+    __device__ static inline void condition(const ModelDev& m, int t, State& st, long long new_infectious, double& lw)
+    {
+        long long z = st.c[8] + new_infectious;
+        const long long y = (long long)m.y[t];
+        if (y != -1) {
+            lw = lw + log_binomial_pmf(y, z, st.r[5]);
+            z = 0;
+        }
+        st.c[8] = z;
+    }
+
+    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
+                                         Stream& s, bool& ckpt)
+    {
+        ckpt = true;
+        const long long n = (long long)m.p[0];
+        if (b == 0) {
+            st.r[0] = (double)(Real)rate(s, m.p[1], 1.0, 1.0);
+            st.r[1] = (double)(Real)rate(s, m.p[2], 1.0 + 2.0 / 4.4, 3.0 - 2.0 / 4.4);
+            st.r[2] = (double)(Real)rate(s, m.p[3], 1.0 + 2.0 / 4.5, 3.0 - 2.0 / 4.5);
+            st.r[3] = (double)(Real)rate(s, m.p[4], 1.0, 1.0);
+            st.r[4] = (double)(Real)rate(s, m.p[5], 1.0 + 2.0 / 6.5, 3.0 - 2.0 / 6.5);
+            st.r[5] = (double)(Real)rate(s, m.p[6], 1.0, 1.0);
+            const long long hI = m.p[8] >= 0.0 ? (long long)m.p[8] : 1 + (long long)draw_poisson(s, 5.0);
+            const long long hE = m.p[7] >= 0.0 ? (long long)m.p[7] : (long long)draw_poisson(s, 5.0);
+            const long long hR = m.p[9] >= 0.0
+                                     ? (long long)m.p[9]
+                                     : (long long)__builtin_floor(draw_uniform(s, 0.0, (double)(n - hI - hE + 1)));
+            const long long mS = m.p[10] >= 0.0
+                                     ? (long long)m.p[10]
+                                     : (long long)__builtin_floor((double)n * fn::exp(draw_uniform(s, -1.0, 2.0) * m.ln10));
+            st.c[0] = n - hE - hI - hR;
+            st.c[1] = hE;
+            st.c[2] = hI;
+            st.c[3] = hR;
+            st.c[4] = mS;
+            st.c[5] = st.c[6] = st.c[7] = 0;
+            st.c[8] = 0;
+            condition(m, 0, st, hI, lw);
+            return m.T > 1 ? 1 : kStop;
+        }
+        const int t = (int)round;
+        const double hLambda = st.r[0], hDelta = st.r[1], hGamma = st.r[2];
+        const double mLambda = st.r[3], mDelta = st.r[4];
+        const double mNu = 1.0 / 7.0, mMu = 6.0 / 7.0, mGamma = 0.0;
+        const long long hSP = st.c[0], hEP = st.c[1], hIP = st.c[2], hRP = st.c[3];
+        const long long mSP = st.c[4], mEP = st.c[5], mIP = st.c[6], mRP = st.c[7];
+        // humans
+        const long long hN = hSP + hEP + hIP + hRP;
+        const long long hTau = draw_binomial(s, hSP, 1.0 - fn::exp(-((double)mIP / (double)hN)));
+        const long long hDeltaE = draw_binomial(s, hTau, hLambda);
+        const long long hDeltaI = draw_binomial(s, hEP, hDelta);
+        const long long hDeltaR = draw_binomial(s, hIP, hGamma);
+        st.c[0] = hSP - hDeltaE;
+        st.c[1] = hEP + hDeltaE - hDeltaI;
+        st.c[2] = hIP + hDeltaI - hDeltaR;
+        st.c[3] = hRP + hDeltaR;
+        // mosquitoes
+        const long long mTau = draw_binomial(s, mSP, 1.0 - fn::exp(-((double)hIP / (double)hN)));
+        const long long mN = mSP + mEP + mIP + mRP;
+        const long long mDeltaE = draw_binomial(s, mTau, mLambda);
+        const long long mDeltaI = draw_binomial(s, mEP, mDelta);
+        const long long mDeltaR = draw_binomial(s, mIP, mGamma);
+        long long mS = mSP - mDeltaE;
+        long long mE = mEP + mDeltaE - mDeltaI;
+        long long mI = mIP + mDeltaI - mDeltaR;
+        long long mR = mRP + mDeltaR;
+        mS = draw_binomial(s, mS, mMu);
+        mE = draw_binomial(s, mE, mMu);
+        mI = draw_binomial(s, mI, mMu);
+        mR = draw_binomial(s, mR, mMu);
+        const long long mDeltaS = draw_binomial(s, mN, mNu);
+        st.c[4] = mS + mDeltaS;
+        st.c[5] = mE;
+        st.c[6] = mI;
+        st.c[7] = mR;
+        condition(m, t, st, hDeltaI, lw);
+        return t + 1 < m.T ? 1 : kStop;
     }
 };
 
