@@ -12,8 +12,8 @@ kernel's achieved bandwidth against MI355X's HBM peak, and the CPU oracle's
 throughput on a bounded sample of the same workload. Beside the headline: the
 same workload at 2^24 particles (buffers beyond the Infinity Cache), 512
 batched ClaDS runs of 4096 particles, and a serving stream (one-at-a-time vs
-continuous batching, p50/p99 latency), and the headline workload with
-ESS-triggered resampling.
+continuous batching, p50/p99 latency), the headline workload with
+ESS-triggered resampling, and the vector-borne disease (SEIR) model.
 """
 from __future__ import annotations
 
@@ -169,6 +169,45 @@ def ess_point(smc, ctx, spec, n: int, tau: float = 0.5, runs: int = 3):
             "block_steps_per_s": s["block_steps"] / (ms / 1e3), "log_z_last": s["log_z"]}
 
 
+def seir_point(smc, ctx, I, n: int = 1 << 16, days: int = 100, runs: int = 3, cpu: bool = True):
+    """The vector-borne disease (SEIR) model of the paper's second experiment
+    on a synthetic 100-day outbreak (the dengue data is not available), with
+    the listing's priors: complete runs on the GPU, and the oracle on a
+    bounded sample for scale."""
+    import torch
+    y = I.seir_data(days, 6000)
+    spec = I.seir_spec(y, 32)
+    model = smc.Model(ctx, spec)
+    run = smc.Run(model, n, 61)
+    run.run_to_end()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    for i in range(runs):
+        run.reset(62 + i)
+        run.run_to_end()
+    end.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / runs
+    s = run.stats()
+    run.close()
+    model.close()
+    out = {"workload": f"seir_synthetic{days}d_n{n}", "particles": n, "days": days, "runs": runs,
+           "ms_per_run": ms, "status": s["status"], "log_z_last": s["log_z"],
+           "block_steps_per_s": s["block_steps"] / (ms / 1e3)}
+    if cpu:
+        from oracle import oracle as O
+        m = 1 << 12
+        t0 = time.perf_counter()
+        r = O.Run(spec, m, 61)
+        r.run_to_end()
+        dt = time.perf_counter() - t0
+        out["cpu_oracle_block_steps_per_s"] = r.block_steps / dt
+        out["cpu_oracle_sample"] = f"{m} particles, all {days} days, single thread, {dt:.1f} s"
+    return out
+
+
 def large_point(smc, model, n: int, runs: int = 2):
     """Complete runs at a particle count whose buffers exceed the 256 MB
     Infinity Cache, so every round streams from HBM."""
@@ -208,6 +247,7 @@ def main():
                     help="arrival rates as multiples of the one-at-a-time service rate, comma-separated")
     ap.add_argument("--no-large", action="store_true", help="skip the 2^24-particle point")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS-triggered point")
+    ap.add_argument("--no-seir", action="store_true", help="skip the vector-borne disease (SEIR) point")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -329,6 +369,9 @@ def main():
     if not args.no_ess:
         print("ESS-triggered point", file=sys.stderr, flush=True)
         out["ess"] = ess_point(smc, ctx, spec, N_PARTICLES)
+    if not args.no_seir:
+        print("SEIR point", file=sys.stderr, flush=True)
+        out["seir"] = seir_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
     if not args.no_large:
         print("2^24-particle point", file=sys.stderr, flush=True)
         out["large"] = large_point(smc, model, 1 << 24)
