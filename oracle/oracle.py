@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c11",
           "-Wall", "-Wextra"]
 
-KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3, "seir": 4}
+KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3, "seir": 4, "crbd_ds": 5}
 STOP = 255
 OK, FINISHED, ERR_INVALID, ERR_NAN, DEGENERATE = 0, 1, -1, -5, -6
 READ_BLK, READ_LW, READ_ANC, READ_FIELD0 = 0, 1, 2, 16
@@ -157,9 +157,11 @@ def log_binomial_pmf(y, z, p):
 
 
 def sample(kind, a, b, seed, count):
-    """count draws from one stream: kind "binomial" (n=a, p=b), "gamma" (shape a), "beta" (a, b)."""
+    """count draws from one stream: kind "binomial" (n=a, p=b), "gamma" (shape a), "beta" (a, b),
+    "negbin" (Poisson count with rate ~ Gamma(a, scale b)), "lomax" (Exponential lifetime with
+    rate ~ Gamma(a, scale b))."""
     out = np.zeros(int(count), dtype=np.float64)
-    code = {"binomial": 0, "gamma": 1, "beta": 2}[kind]
+    code = {"binomial": 0, "gamma": 1, "beta": 2, "negbin": 3, "lomax": 4}[kind]
     lib().or_sample(code, float(a), float(b), int(seed), int(count), _ptr(out, C.c_double))
     return out
 
@@ -199,8 +201,8 @@ def _model_struct(spec, keep):
     return m
 
 
-N_REAL = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4, "seir": 6}
-N_INT = {"geometric": 1, "lgssm": 1, "crbd": 1, "clads": 2, "seir": 10}
+N_REAL = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4, "seir": 6, "crbd_ds": 4}
+N_INT = {"geometric": 1, "lgssm": 1, "crbd": 1, "clads": 2, "seir": 10, "crbd_ds": 1}
 
 
 def propagate_particle(spec, seed, slot, rnd, blk, reals, ints, stack=None, stack_depth=0):

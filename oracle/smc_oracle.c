@@ -416,16 +416,44 @@ double or_log_binomial_pmf(int64_t y, int64_t z, double p)
     return lw;
 }
 
+/* Negative Binomial predictive of a Poisson(lambda t) count, lambda ~
+ * Gamma(a, th): inversion by sequential search; -1 beyond the event cap. */
+static int64_t neg_binomial_draw(stream* s, double a, double th, double t)
+{
+    double lq = or_log(1.0 + th * t);
+    double pk = or_exp(-a * lq);
+    double q = th * t / (1.0 + th * t);
+    double u = next_uniform(s);
+    int64_t k = 0;
+    while (u > pk) {
+        if (k >= OR_POISSON_MAX_K) return -1;
+        u = u - pk;
+        k += 1;
+        pk = pk * (((double)(k - 1) + a) / (double)k * q);
+    }
+    return k;
+}
+
+static double lomax_draw(stream* s, double a, double th)
+{
+    double u = next_uniform(s);
+    return (or_exp(-or_log(u) / a) - 1.0) / th;
+}
+
 /* Sampler checks: `count` draws in sequence from the stream of (seed,
  * particle 0, round 0, tag 0). kind 0: Binomial(n = a, p = b); 1: Gamma(a);
- * 2: Beta(a, b). Results as doubles. */
+ * 2: Beta(a, b); 3: the Negative Binomial predictive of a Poisson(lambda) count
+ * with lambda ~ Gamma(a, b); 4: the Lomax predictive of an Exponential(mu)
+ * lifetime with mu ~ Gamma(a, b). Results as doubles. */
 void or_sample(int32_t kind, double a, double b, uint64_t seed, int64_t count, double* out)
 {
     stream s = {seed, 0, 0, OR_TAG_PROPAGATE, 0};
     for (int64_t i = 0; i < count; ++i) {
         if (kind == 0) out[i] = (double)binomial_draw(&s, (int64_t)a, b);
         else if (kind == 1) out[i] = gamma_mt(&s, a);
-        else out[i] = beta_draw(&s, a, b);
+        else if (kind == 2) out[i] = beta_draw(&s, a, b);
+        else if (kind == 3) out[i] = (double)neg_binomial_draw(&s, a, b, 1.0);
+        else out[i] = lomax_draw(&s, a, b);
     }
 }
 
@@ -575,6 +603,111 @@ static int crbd_block(or_run* r, uint64_t i, int b, stream* s, int* ckpt)
             }
         }
     }
+    r->lw[i] = r->lw[i] + (ln_p1 + (ln_p2 + ln_p3));
+    r->ints[0][i] = node + 1;
+    return node + 1 < r->m.n_nodes ? 1 : (int)OR_STOP;
+}
+
+/* ------------------------------------------------------------------------- */
+/* CRBD with static delayed sampling (Sec. 5.3 runs CRBD "with delayed        */
+/* sampling"; the paper gives no derivation, this is the library's reading):  */
+/* lambda ~ Gamma(k, theta) and mu ~ Gamma(k, theta) are never sampled; each  */
+/* particle carries their posterior shapes and scales and every quantity that */
+/* depends on a rate is drawn from, or weighted by, its predictive under the  */
+/* current posterior, which is then updated by conjugacy:                     */
+/*  - survival of an observed branch of length t, factor exp(-mu t):          */
+/*      lw += -a_mu log(1 + th_mu t);  th_mu <- th_mu / (1 + th_mu t);         */
+/*  - the speciation factor lambda at an internal node:                       */
+/*      lw += log(a_l th_l);  a_l <- a_l + 1;                                  */
+/*  - a count K ~ Poisson(lambda t): K from the Negative Binomial predictive  */
+/*      P(K = k) = C(k + a - 1, k) p^a (1 - p)^k, p = 1 / (1 + th t),         */
+/*      by inversion with one uniform (more than the event cap: -1);          */
+/*      a_l <- a_l + K;  th_l <- th_l / (1 + th_l t);                          */
+/*  - a lifetime d ~ Exponential(mu): the Lomax predictive by inversion,      */
+/*      d = (exp(-log(u) / a_mu) - 1) / th_mu;                                 */
+/*      a_mu <- a_mu + 1;  th_mu <- th_mu / (1 + th_mu d).                     */
+/* Everything else (program order, caps, the detection of hidden lineages,    */
+/* lw += l1 + (l2 + l3)) is as in crbd_block. The priors: p[1], p[2] are the  */
+/* scales of the shape-1 Gamma priors of lambda and mu.                       */
+/* Fields: real0..3 = a_l, th_l, a_mu, th_mu; int0 = node cursor.             */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    stream* s;
+    double a_l, th_l, a_mu, th_mu, rho;
+    int events, max_events, max_depth;
+} crbd_ds_ctx;
+
+static int crbd_ds_undetected(crbd_ds_ctx* c, double t_start, int depth)
+{
+    if (depth > c->max_depth) return 0;
+    double duration = lomax_draw(c->s, c->a_mu, c->th_mu);
+    c->a_mu = c->a_mu + 1.0;
+    c->th_mu = c->th_mu / (1.0 + c->th_mu * duration);
+    if (duration > t_start) {
+        if (bernoulli(c->s, c->rho)) return 0;
+    }
+    double branch_len = duration < t_start ? duration : t_start;
+    int64_t n = neg_binomial_draw(c->s, c->a_l, c->th_l, branch_len);
+    if (n < 0) return 0;
+    c->a_l = c->a_l + (double)n;
+    c->th_l = c->th_l / (1.0 + c->th_l * branch_len);
+    for (int64_t e = 0; e < n; ++e) {
+        if (c->events >= c->max_events) return 0;
+        c->events += 1;
+        double t = uniform_ab(c->s, t_start - branch_len, t_start);
+        if (!crbd_ds_undetected(c, t, depth + 1)) return 0;
+    }
+    return 1;
+}
+
+static int crbd_ds_block(or_run* r, uint64_t i, int b, stream* s, int* ckpt)
+{
+    const double* p = r->m.p;
+    *ckpt = 1;
+    if (b == 0) {
+        r->real[0][i] = store_p(r, 1.0);
+        r->real[1][i] = store_p(r, p[1]);
+        r->real[2][i] = store_p(r, 1.0);
+        r->real[3][i] = store_p(r, p[2]);
+        r->lw[i] = r->lw[i] + r->corr;
+        r->ints[0][i] = 1;
+        return r->m.n_nodes > 1 ? 1 : (int)OR_STOP;
+    }
+    int node = r->ints[0][i];
+    int par = r->m.parent[node];
+    crbd_ds_ctx c = {s, r->real[0][i], r->real[1][i], r->real[2][i], r->real[3][i], p[0], 0, (int)p[5], (int)p[6]};
+    double t_p = r->m.age[par], t_c = r->m.age[node];
+    double len = t_p - t_c;
+    double ln_p1 = -c.a_mu * or_log(1.0 + c.th_mu * len);
+    c.th_mu = c.th_mu / (1.0 + c.th_mu * len);
+    double ln_p2 = r->log_rho;
+    if (r->m.left[node] >= 0) {
+        ln_p2 = or_log(c.a_l * c.th_l);
+        c.a_l = c.a_l + 1.0;
+    }
+    int64_t n = neg_binomial_draw(s, c.a_l, c.th_l, len);
+    double ln_p3 = 0.0;
+    if (n < 0) {
+        ln_p3 = -INFINITY;
+    } else {
+        c.a_l = c.a_l + (double)n;
+        c.th_l = c.th_l / (1.0 + c.th_l * len);
+        for (int64_t e = 0; e < n; ++e) {
+            if (c.events >= c.max_events) { ln_p3 = -INFINITY; break; }
+            c.events += 1;
+            double t = uniform_ab(s, t_c, t_p);
+            if (crbd_ds_undetected(&c, t, 1)) {
+                ln_p3 = ln_p3 + r->ln2;
+            } else {
+                ln_p3 = -INFINITY;
+                break;
+            }
+        }
+    }
+    r->real[0][i] = store_p(r, c.a_l);
+    r->real[1][i] = store_p(r, c.th_l);
+    r->real[2][i] = store_p(r, c.a_mu);
+    r->real[3][i] = store_p(r, c.th_mu);
     r->lw[i] = r->lw[i] + (ln_p1 + (ln_p2 + ln_p3));
     r->ints[0][i] = node + 1;
     return node + 1 < r->m.n_nodes ? 1 : (int)OR_STOP;
@@ -817,6 +950,7 @@ static int sim(or_run* r, uint64_t i, int b, stream* s, int* ckpt)
     case OR_LGSSM: return lgssm_block(r, i, b, s, ckpt);
     case OR_CRBD: return crbd_block(r, i, b, s, ckpt);
     case OR_SEIR: return seir_block(r, i, b, s, ckpt);
+    case OR_CRBD_DS: return crbd_ds_block(r, i, b, s, ckpt);
     default: return clads_block(r, i, b, s, ckpt);
     }
 }
@@ -838,10 +972,11 @@ static int tree_stack_depth(const or_model* m)
 or_run* or_create(const or_model* m, uint64_t n, uint64_t seed)
 {
     if (n == 0 || n > (1ull << 24)) return NULL;
-    if (m->kind < OR_GEOMETRIC || m->kind > OR_SEIR) return NULL;
+    if (m->kind < OR_GEOMETRIC || m->kind > OR_CRBD_DS) return NULL;
     if (m->kind == OR_SEIR && (m->T < 1 || !m->y || !(m->p[0] >= 1.0 && m->p[0] <= 1e8))) return NULL;
     if (m->precision != 32 && m->precision != 64) return NULL;
-    if ((m->kind == OR_CRBD || m->kind == OR_CLADS) && (m->n_nodes < 1 || !m->parent || !m->age || !m->left))
+    if ((m->kind == OR_CRBD || m->kind == OR_CLADS || m->kind == OR_CRBD_DS) &&
+        (m->n_nodes < 1 || !m->parent || !m->age || !m->left))
         return NULL;
     if (m->kind == OR_LGSSM && (m->T < 1 || !m->y)) return NULL;
     if (!(m->ess_threshold >= 0.0 && m->ess_threshold <= 1.0)) return NULL;
@@ -856,6 +991,7 @@ or_run* or_create(const or_model* m, uint64_t n, uint64_t seed)
     case OR_LGSSM: r->n_real = 1; r->n_int = 1; break;
     case OR_CRBD: r->n_real = 2; r->n_int = 1; break;
     case OR_SEIR: r->n_real = 6; r->n_int = 10; break;
+    case OR_CRBD_DS: r->n_real = 4; r->n_int = 1; break;
     default: r->n_real = 4; r->n_int = 2; break;
     }
     r->ln10 = or_log(10.0);
@@ -870,7 +1006,7 @@ or_run* or_create(const or_model* m, uint64_t n, uint64_t seed)
         r->obs_var = m->p[3] * m->p[3];
         r->obs_c = -0.5 * or_log(OR_TWO_PI * r->obs_var);
     }
-    if (m->kind == OR_CRBD || m->kind == OR_CLADS) {
+    if (m->kind == OR_CRBD || m->kind == OR_CLADS || m->kind == OR_CRBD_DS) {
         r->tips = (m->n_nodes + 1) / 2;
         r->log_rho = or_log(m->p[0]);
         double log_fact = 0.0;

@@ -29,14 +29,14 @@
 extern "C" {
 #endif
 
-enum { OR_GEOMETRIC = 0, OR_LGSSM = 1, OR_CRBD = 2, OR_CLADS = 3, OR_SEIR = 4 };
+enum { OR_GEOMETRIC = 0, OR_LGSSM = 1, OR_CRBD = 2, OR_CLADS = 3, OR_SEIR = 4, OR_CRBD_DS = 5 };
 enum { OR_OK = 0, OR_FINISHED = 1, OR_ERR_INVALID = -1, OR_ERR_NAN = -5, OR_DEGENERATE = -6 };
 enum { OR_TAG_PROPAGATE = 0, OR_TAG_RESAMPLE = 1 };
 #define OR_STOP 255u
 
 /* Model description. Parameters are read per model kind (see smc_oracle.c). */
 typedef struct {
-    int32_t kind;       /* OR_GEOMETRIC .. OR_SEIR */
+    int32_t kind;       /* OR_GEOMETRIC .. OR_CRBD_DS */
     int32_t precision;  /* 32 or 64: storage precision of real-valued particle state */
     int32_t checkpoint; /* geometric only: 1 = checkpoint after each heads, 0 = none */
     int32_t n_nodes;    /* trees: 2*tips-1 nodes in preorder, root = 0 */

@@ -154,6 +154,15 @@ def crbd_spec(tree, precision=64, rho=1.0, scale_lambda=1.0, scale_mu=0.5,
                        float(max_events), float(max_depth)]}
 
 
+def crbd_ds_spec(tree, precision=64, rho=1.0, scale_lambda=1.0, scale_mu=0.5,
+                 max_events=MAX_EVENTS, max_depth=MAX_DEPTH) -> dict:
+    """CRBD with static delayed sampling: the Gamma(1, scale) priors of lambda
+    and mu are carried as posteriors instead of being sampled. Parameter
+    positions as for CRBD (fixed-rate entries unused)."""
+    return {"kind": "crbd_ds", "precision": precision, "tree": tree,
+            "params": [rho, scale_lambda, scale_mu, -1.0, -1.0, float(max_events), float(max_depth)]}
+
+
 def clads_spec(tree, precision=32, rho=1.0, scale_l0=1.0, eps=(0.0, 1.0), alpha=(0.8, 1.1),
                scale_sigma=0.2, max_events=MAX_EVENTS, max_depth=MAX_DEPTH,
                fixed_l0=0.0, fixed_eps=-1.0, fixed_alpha=0.0, fixed_sigma=-1.0) -> dict:
