@@ -83,7 +83,8 @@ enum {
     SMC_MODEL_LGSSM = 1,     /* eq. (2), Fig. 4: linear-Gaussian state-space model */
     SMC_MODEL_CRBD = 2,      /* Appendix B listing: constant-rate birth-death */
     SMC_MODEL_CLADS = 3,     /* birth-death with cladogenetic rate shifts */
-    SMC_MODEL_SEIR = 4       /* Appendix listing: vector-borne disease (SEIR) */
+    SMC_MODEL_SEIR = 4,      /* Appendix listing: vector-borne disease (SEIR) */
+    SMC_MODEL_CRBD_DS = 5    /* CRBD with static delayed sampling (Sec. 5.3) */
 };
 
 /* Model description (all pointers are host memory, deep-copied to the device
@@ -101,6 +102,15 @@ enum {
  *   CLADS      {rho, lambda0 scale, eps lo, eps hi, alpha lo, alpha hi,
  *              sigma scale, max events, max depth, fixed lambda0 (>0),
  *              fixed eps (>=0), fixed alpha (>0), fixed sigma (>=0)}.
+ *   CRBD_DS    as CRBD (fixed-rate entries unused; the prior scales must be
+ *              positive): lambda and mu are not sampled but marginalised by
+ *              Gamma conjugacy, each particle carrying their posterior shape
+ *              and scale (fields a_lambda, th_lambda, a_mu, th_mu, then the
+ *              node). Hidden speciation counts come from the Negative Binomial
+ *              predictive and hidden lifetimes from the Lomax predictive;
+ *              branch survival weighs -a_mu log(1 + th_mu t) and an observed
+ *              speciation log(a_lambda th_lambda), each followed by the
+ *              conjugate update.
  *   SEIR       {humans n in [1, 10^7], fixed hLambda, hDelta, hGamma, mLambda,
  *              mDelta, rho (each in [0, 1]; < 0 draws it from the listing's
  *              Beta prior), fixed initial hE, hI, hR, mS (integers; < 0 draws
@@ -256,7 +266,10 @@ smc_status smc_batch_destroy(smc_batch* b); /* NULL-safe */
  * in[3i+1]) and 8 Gamma(in[3i]) (in[3i+1] < 0) or Beta(in[3i], in[3i+1]), each
  * the first draw of the stream of seed in[3i+2], particle 0, round 0, tag 0;
  * 9 log k! of k = in[i]; 10 log of the Binomial(in[3i+1], in[3i+2])
- * probability of in[3i]. */
+ * probability of in[3i]; 11 the Negative Binomial predictive of a
+ * Poisson(rate) count and 12 the Lomax predictive of an Exponential(rate)
+ * lifetime, rate ~ Gamma(shape in[3i], scale in[3i+1]), first draw of the
+ * stream of seed in[3i+2]. */
 smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n);
 /* Philox4x32-10 on n counters: ctr (device, 4 x uint32 each), key (2 x uint32
  * each), out (device, 4 x uint32 each). */

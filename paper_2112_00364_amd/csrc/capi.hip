@@ -91,13 +91,14 @@ int real_fields(int kind)
     case SMC_MODEL_CRBD: return 2;
     case SMC_MODEL_CLADS: return 4;
     case SMC_MODEL_SEIR: return 6;
+    case SMC_MODEL_CRBD_DS: return 4;
     default: return 0;
     }
 }
 int stored_int_fields(int kind) { return kind == SMC_MODEL_GEOMETRIC ? 1 : kind == SMC_MODEL_SEIR ? 9 : 0; }
 // Int fields as the model defines them (cursor-like ones follow the round and
 // are not stored): geometric flips; LGSSM t; CRBD node; ClaDS node and stack
-// size; SEIR nine counts and the day.
+// size; SEIR nine counts and the day; delayed-sampling CRBD node.
 int logical_int_fields(int kind) { return kind == SMC_MODEL_CLADS ? 2 : kind == SMC_MODEL_SEIR ? 10 : 1; }
 
 }  // namespace
@@ -279,7 +280,8 @@ smc_status do_resample(smc_run* r)
 uint32_t lockstep_rounds(const smc_model* m)
 {
     if (m->kind == SMC_MODEL_LGSSM || m->kind == SMC_MODEL_SEIR) return (uint32_t)m->T;
-    if (m->kind == SMC_MODEL_CRBD || m->kind == SMC_MODEL_CLADS) return (uint32_t)m->n_nodes;
+    if (m->kind == SMC_MODEL_CRBD || m->kind == SMC_MODEL_CLADS || m->kind == SMC_MODEL_CRBD_DS)
+        return (uint32_t)m->n_nodes;
     return 0;
 }
 
@@ -325,9 +327,9 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
 {
     if (!ctx || !d || !out) return fail(SMC_ERR_INVALID, "NULL argument");
     *out = nullptr;
-    if (d->kind < SMC_MODEL_GEOMETRIC || d->kind > SMC_MODEL_SEIR) return fail(SMC_ERR_INVALID, "unknown model kind");
+    if (d->kind < SMC_MODEL_GEOMETRIC || d->kind > SMC_MODEL_CRBD_DS) return fail(SMC_ERR_INVALID, "unknown model kind");
     if (d->precision != 32 && d->precision != 64) return fail(SMC_ERR_INVALID, "precision must be 32 or 64");
-    const bool tree = d->kind == SMC_MODEL_CRBD || d->kind == SMC_MODEL_CLADS;
+    const bool tree = d->kind == SMC_MODEL_CRBD || d->kind == SMC_MODEL_CLADS || d->kind == SMC_MODEL_CRBD_DS;
     if (tree) {
         if (d->n_nodes < 1 || d->n_nodes > 1 << 20 || !d->parent || !d->left || !d->age)
             return fail(SMC_ERR_INVALID, "tree arrays missing or empty");
@@ -335,11 +337,13 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
         for (int i = 1; i < d->n_nodes; ++i)
             if (d->parent[i] < 0 || d->parent[i] >= i || !(d->age[d->parent[i]] >= d->age[i]))
                 return fail(SMC_ERR_INVALID, "tree is not in preorder with ages decreasing from the root");
-        const int ev = d->kind == SMC_MODEL_CRBD ? 5 : 7;
+        const int ev = d->kind == SMC_MODEL_CLADS ? 7 : 5;
         if (!(d->params[ev + 1] >= 1.0 && d->params[ev + 1] <= 32.0))
             return fail(SMC_ERR_INVALID, "max depth must be in [1, 32]");
         if (!(d->params[ev] >= 0.0 && d->params[ev] <= 1e6)) return fail(SMC_ERR_INVALID, "max events must be in [0, 10^6]");
         if (!(d->params[0] > 0.0 && d->params[0] <= 1.0)) return fail(SMC_ERR_INVALID, "rho must be in (0, 1]");
+        if (d->kind == SMC_MODEL_CRBD_DS && !(d->params[1] > 0.0 && d->params[2] > 0.0))
+            return fail(SMC_ERR_INVALID, "prior scales must be positive");
     }
     if ((d->kind == SMC_MODEL_LGSSM || d->kind == SMC_MODEL_SEIR) && (d->T < 1 || d->T > (1 << 24) || !d->y))
         return fail(SMC_ERR_INVALID, "observations missing");
@@ -926,7 +930,7 @@ smc_status smc_batch_destroy(smc_batch* b)
 smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n)
 {
     if (!ctx || !in || !out) return fail(SMC_ERR_INVALID, "NULL argument");
-    if (op < 0 || op > 10) return fail(SMC_ERR_INVALID, "unknown op");
+    if (op < 0 || op > 12) return fail(SMC_ERR_INVALID, "unknown op");
     if (n == 0) return SMC_OK;
     HIP_TRY(launch_selftest_math(op, in, out, n, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -380,6 +380,32 @@ __device__ inline long long draw_binomial(Stream& s, long long n, double p)
     return flip ? n - k : k;
 }
 
+// Delayed sampling under Gamma(a, th) posteriors (shape, scale):
+// the Negative Binomial predictive of a Poisson(rate t) count, by inversion
+// (-1 beyond the event cap), and the Lomax predictive of an
+// Exponential(rate) lifetime, by inversion.
+__device__ inline long long draw_neg_binomial(Stream& s, double a, double th, double t)
+{
+    const double lq = fn::log(1.0 + th * t);
+    double pk = fn::exp(-a * lq);
+    const double q = th * t / (1.0 + th * t);
+    double u = s.uniform();
+    long long k = 0;
+    while (u > pk) {
+        if (k >= fn::kMaxInversionSteps) return -1;
+        u = u - pk;
+        k += 1;
+        pk = pk * (((double)(k - 1) + a) / (double)k * q);
+    }
+    return k;
+}
+
+__device__ inline double draw_lomax(Stream& s, double a, double th)
+{
+    const double u = s.uniform();
+    return (fn::exp(-fn::log(u) / a) - 1.0) / th;
+}
+
 // log of the Binomial(z, p) probability of y, with 0 log 0 = 0.
 __device__ inline double log_binomial_pmf(long long y, long long z, double p)
 {

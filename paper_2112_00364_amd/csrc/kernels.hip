@@ -396,6 +396,28 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint64_t
         }
         store_real<Real>(out.real[0], j, st.lambda);
         store_real<Real>(out.real[1], j, st.mu);
+    } else if constexpr (Kind == 5) {
+        using Stack = typename CrbdStack<kDeep>::type;
+        Stack stack;
+        if constexpr (kDeep) stack.base = static_cast<CrbdFrame*>(lds_stack);
+        typename CrbdDs<Real>::State st{0.0, 0.0, 0.0, 0.0};
+        if (round > 0) {
+            st.a_l = load_real<Real>(in.real[0], src);
+            st.th_l = load_real<Real>(in.real[1], src);
+            st.a_mu = load_real<Real>(in.real[2], src);
+            st.th_mu = load_real<Real>(in.real[3], src);
+        }
+        while (blk != kStop) {
+            bool ck = false;
+            blk = CrbdDs<Real>::template sim<Stack>(m, round, blk, st, lw, s, ck, overflow, stack);
+            if (overflow) return false;
+            steps += 1;
+            if (ck) break;
+        }
+        store_real<Real>(out.real[0], j, st.a_l);
+        store_real<Real>(out.real[1], j, st.th_l);
+        store_real<Real>(out.real[2], j, st.a_mu);
+        store_real<Real>(out.real[3], j, st.th_mu);
     } else if constexpr (Kind == 4) {
         typename Seir<Real>::State st{};
         if (round > 0) {
@@ -477,7 +499,7 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
     uint32_t steps = 0;
     bool deep = false;
     if (valid) deep = !run_particle<Kind, Real, false>(R, m, seed, j, round, src, lw0, blk, lw, steps, nullptr);
-    if constexpr (Kind == 2) {
+    if constexpr (Kind == 2 || Kind == 5) {
         __shared__ __align__(16) unsigned char s_stack[kPropThreads / 64][kDeepStackBytes];
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         unsigned long long pending = __ballot(deep);
@@ -951,6 +973,18 @@ __global__ void k_selftest_math(int op, const double* __restrict__ in, double* _
         r = in[3 * i + 1] < 0.0 ? draw_gamma(s, in[3 * i]) : draw_beta(s, in[3 * i], in[3 * i + 1]);
         break;
     }
+    case 11: {  // in: (a, th, seed) -> Negative Binomial predictive of a Poisson(rate) count, rate ~ Gamma(a, th)
+        Stream s;
+        s.start((uint64_t)in[3 * i + 2], 0u, 0u, kTagPropagate);
+        r = (double)draw_neg_binomial(s, in[3 * i], in[3 * i + 1], 1.0);
+        break;
+    }
+    case 12: {  // in: (a, th, seed) -> Lomax predictive of an Exponential(rate) lifetime
+        Stream s;
+        s.start((uint64_t)in[3 * i + 2], 0u, 0u, kTagPropagate);
+        r = draw_lomax(s, in[3 * i], in[3 * i + 1]);
+        break;
+    }
     case 9: r = log_factorial((long long)in[i]); break;
     case 10: r = log_binomial_pmf((long long)in[3 * i], (long long)in[3 * i + 1], in[3 * i + 2]); break;
     default: r = 0.0;
@@ -1003,7 +1037,7 @@ __global__ void k_model_setup(ModelDev* m)
         m->obs_c = -0.5 * fn::log(fn::kTau * m->obs_var);
     }
     m->ln10 = fn::log(10.0);
-    if (m->kind == 2 || m->kind == 3) {
+    if (m->kind == 2 || m->kind == 3 || m->kind == 5) {
         const int tips = (m->n_nodes + 1) / 2;
         m->log_rho = fn::log(m->p[0]);
         double log_fact = 0.0;
@@ -1027,8 +1061,10 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     else if (kind == 2) hipLaunchKernelGGL((k_propagate<2, double>), g, b, 0, st, runs, tiles);
     else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate<3, float>), g, b, 0, st, runs, tiles);
     else if (kind == 3) hipLaunchKernelGGL((k_propagate<3, double>), g, b, 0, st, runs, tiles);
-    else if (precision == 32) hipLaunchKernelGGL((k_propagate<4, float>), g, b, 0, st, runs, tiles);
-    else hipLaunchKernelGGL((k_propagate<4, double>), g, b, 0, st, runs, tiles);
+    else if (kind == 4 && precision == 32) hipLaunchKernelGGL((k_propagate<4, float>), g, b, 0, st, runs, tiles);
+    else if (kind == 4) hipLaunchKernelGGL((k_propagate<4, double>), g, b, 0, st, runs, tiles);
+    else if (precision == 32) hipLaunchKernelGGL((k_propagate<5, float>), g, b, 0, st, runs, tiles);
+    else hipLaunchKernelGGL((k_propagate<5, double>), g, b, 0, st, runs, tiles);
     return hipGetLastError();
 }
 
@@ -1042,8 +1078,10 @@ hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipS
     else if (kind == 2) hipLaunchKernelGGL((k_propagate_one<2, double>), g, b, 0, st, run);
     else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate_one<3, float>), g, b, 0, st, run);
     else if (kind == 3) hipLaunchKernelGGL((k_propagate_one<3, double>), g, b, 0, st, run);
-    else if (precision == 32) hipLaunchKernelGGL((k_propagate_one<4, float>), g, b, 0, st, run);
-    else hipLaunchKernelGGL((k_propagate_one<4, double>), g, b, 0, st, run);
+    else if (kind == 4 && precision == 32) hipLaunchKernelGGL((k_propagate_one<4, float>), g, b, 0, st, run);
+    else if (kind == 4) hipLaunchKernelGGL((k_propagate_one<4, double>), g, b, 0, st, run);
+    else if (precision == 32) hipLaunchKernelGGL((k_propagate_one<5, float>), g, b, 0, st, run);
+    else hipLaunchKernelGGL((k_propagate_one<5, double>), g, b, 0, st, run);
     return hipGetLastError();
 }
 

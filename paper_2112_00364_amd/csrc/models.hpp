@@ -260,6 +260,126 @@ struct Crbd {
 };
 
 // ---------------------------------------------------------------------------
+// CRBD with static delayed sampling (the paper's CRBD experiment with
+// variance-reducing techniques, Sec. 5.3; the derivation is this library's
+// reading). lambda and mu are never sampled: each particle carries their
+// Gamma posteriors (shape a, scale th). Branch survival weighs
+// -a_mu log(1 + th_mu t), an observed speciation log(a_l th_l); hidden
+// speciation counts come from the Negative Binomial predictive and hidden
+// lifetimes from the Lomax predictive; each is followed by its conjugate
+// update. Program order, caps and detection as in Crbd.
+// ---------------------------------------------------------------------------
+struct CrbdDsSim {
+    double a_l, th_l, a_mu, th_mu, rho;
+    int events, max_events, max_depth;
+
+    template <class Stack>
+    __device__ inline int undetected(Stream& s, double t0, Stack& stack)
+    {
+        stack.depth = 0;
+        double enter_at = t0;
+        bool entering = true;
+        while (true) {
+            if (entering) {
+                if (stack.depth + 1 > max_depth) return kDetected;
+                if (stack.full()) return kOverflow;
+                const double life = draw_lomax(s, a_mu, th_mu);
+                a_mu = a_mu + 1.0;
+                th_mu = th_mu / (1.0 + th_mu * life);
+                if (life > enter_at) {
+                    if (draw_bernoulli(s, rho)) return kDetected;
+                }
+                const double len = life < enter_at ? life : enter_at;
+                const long long n = draw_neg_binomial(s, a_l, th_l, len);
+                if (n < 0) return kDetected;
+                a_l = a_l + (double)n;
+                th_l = th_l / (1.0 + th_l * len);
+                stack.push(CrbdFrame{(int)n, enter_at, len});
+                entering = false;
+            }
+            CrbdFrame& top = stack.top();
+            if (top.remaining == 0) {
+                stack.pop();
+                if (stack.depth == 0) return kUndetected;
+                continue;
+            }
+            top.remaining -= 1;
+            if (events >= max_events) return kDetected;
+            events += 1;
+            const double a = top.start - top.length;
+            enter_at = draw_uniform(s, a, top.start);
+            entering = true;
+        }
+    }
+};
+
+template <class Real>
+struct CrbdDs {
+    static constexpr int kReal = 4, kInt = 0;
+    struct State {
+        double a_l, th_l, a_mu, th_mu;
+    };
+
+    template <class Stack>
+    __device__ static inline uint8_t sim(const ModelDev& m, uint32_t round, uint8_t b, State& st, double& lw,
+                                         Stream& s, bool& ckpt, bool& overflow, Stack& stack)
+    {
+        ckpt = true;
+        if (b == 0) {
+            st.a_l = (double)(Real)1.0;
+            st.th_l = (double)(Real)m.p[1];
+            st.a_mu = (double)(Real)1.0;
+            st.th_mu = (double)(Real)m.p[2];
+            lw = lw + m.corr;
+            return m.n_nodes > 1 ? 1 : kStop;
+        }
+        const int node = (int)round;
+        CrbdDsSim c{st.a_l, st.th_l, st.a_mu, st.th_mu, m.p[0], 0, (int)m.p[5], (int)m.p[6]};
+        const double tp = m.age[m.parent[node]], tc = m.age[node];
+        const double len = tp - tc;
+        const double ln1 = -c.a_mu * fn::log(1.0 + c.th_mu * len);
+        c.th_mu = c.th_mu / (1.0 + c.th_mu * len);
+        double ln2 = m.log_rho;
+        if (m.left[node] >= 0) {
+            ln2 = fn::log(c.a_l * c.th_l);
+            c.a_l = c.a_l + 1.0;
+        }
+        const long long n = draw_neg_binomial(s, c.a_l, c.th_l, len);
+        double ln3 = 0.0;
+        if (n < 0) {
+            ln3 = -__builtin_huge_val();
+        } else {
+            c.a_l = c.a_l + (double)n;
+            c.th_l = c.th_l / (1.0 + c.th_l * len);
+            for (long long e = 0; e < n; ++e) {
+                if (c.events >= c.max_events) {
+                    ln3 = -__builtin_huge_val();
+                    break;
+                }
+                c.events += 1;
+                const double t = draw_uniform(s, tc, tp);
+                const int h = c.template undetected<Stack>(s, t, stack);
+                if (h == kOverflow) {
+                    overflow = true;
+                    return b;
+                }
+                if (h == kDetected) {
+                    ln3 = -__builtin_huge_val();
+                    break;
+                }
+                ln3 = ln3 + m.ln2;
+            }
+        }
+        st.a_l = (double)(Real)c.a_l;
+        st.th_l = (double)(Real)c.th_l;
+        st.a_mu = (double)(Real)c.a_mu;
+        st.th_mu = (double)(Real)c.th_mu;
+        lw = lw + (ln1 + (ln2 + ln3));
+        return node + 1 < m.n_nodes ? 1 : kStop;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Birth-death with cladogenetic rate shifts (ClaDS-style). State: current
 // lineage rate lambda, eps, alpha, sigma, plus a stack of pending right-
 // daughter rates (its size is the same for every particle: sp_before[round]).

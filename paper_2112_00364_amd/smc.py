@@ -20,7 +20,7 @@ OK, FINISHED = 0, 1
 ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_STATE, ERR_NAN, DEGENERATE = -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", 1: "FINISHED", -1: "ERR_INVALID", -2: "ERR_OOM", -3: "ERR_DEVICE",
                 -4: "ERR_STATE", -5: "ERR_NAN", -6: "DEGENERATE"}
-KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3, "seir": 4}
+KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3, "seir": 4, "crbd_ds": 5}
 READ_BLK, READ_LW, READ_ANC, READ_FIELD0 = 0, 1, 2, 16
 STOP = 255
 
@@ -30,6 +30,7 @@ FIELDS = {
     "lgssm": (1, ["x", "t"]),
     "crbd": (2, ["lambda", "mu", "node"]),
     "clads": (4, ["lambda", "eps", "alpha", "sigma", "node", "stack_size"]),
+    "crbd_ds": (4, ["a_lambda", "th_lambda", "a_mu", "th_mu", "node"]),
     "seir": (6, ["hLambda", "hDelta", "hGamma", "mLambda", "mDelta", "rho",
                  "hS", "hE", "hI", "hR", "mS", "mE", "mI", "mR", "z", "t"]),
 }
@@ -164,7 +165,7 @@ class Context:
     def selftest_math(self, op: int, x):
         torch = _torch()
         xin = torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).to(f"cuda:{self.device}")
-        n = xin.numel() // (2 if op in (5, 6) else 3 if op in (7, 8, 10) else 1)
+        n = xin.numel() // (2 if op in (5, 6) else 3 if op in (7, 8, 10, 11, 12) else 1)
         out = torch.empty(n, dtype=torch.float64, device=xin.device)
         _check(lib().smc_selftest_math(self._h, op, C.c_void_p(xin.data_ptr()), C.c_void_p(out.data_ptr()), n))
         return out.cpu().numpy()
