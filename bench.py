@@ -13,7 +13,9 @@ throughput on a bounded sample of the same workload. Beside the headline: the
 same workload at 2^24 particles (buffers beyond the Infinity Cache), 512
 batched ClaDS runs of 4096 particles, and a serving stream (one-at-a-time vs
 continuous batching, p50/p99 latency), the headline workload with
-ESS-triggered resampling, and the vector-borne disease (SEIR) model.
+ESS-triggered resampling, the same tree with delayed sampling and ESS-triggered
+resampling (the paper's CRBD experiment with variance-reducing techniques), and
+the vector-borne disease (SEIR) model.
 """
 from __future__ import annotations
 
@@ -208,6 +210,33 @@ def seir_point(smc, ctx, I, n: int = 1 << 16, days: int = 100, runs: int = 3, cp
     return out
 
 
+def crbd_ds_point(smc, ctx, I, tree, n: int, tau: float = 0.5, runs: int = 3):
+    """The paper's CRBD experiment with variance-reducing techniques: the
+    headline tree with static delayed sampling (rates marginalised) and
+    ESS-triggered resampling."""
+    import torch
+    model = smc.Model(ctx, dict(I.crbd_ds_spec(tree, precision=32), ess_threshold=tau))
+    run = smc.Run(model, n, 71)
+    run.run_to_end()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    zs = []
+    for i in range(runs):
+        run.reset(72 + i)
+        run.run_to_end()
+    end.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / runs
+    s = run.stats()
+    run.close()
+    model.close()
+    return {"workload": f"crbd_ds_yule{TIPS}_n{n}", "ess_threshold": tau, "particles": n, "runs": runs,
+            "ms_per_run": ms, "status": s["status"], "resampled_rounds": s["resamples"], "rounds": s["round"] + 1,
+            "block_steps_per_s": s["block_steps"] / (ms / 1e3), "log_z_last": s["log_z"]}
+
+
 def large_point(smc, model, n: int, runs: int = 2):
     """Complete runs at a particle count whose buffers exceed the 256 MB
     Infinity Cache, so every round streams from HBM."""
@@ -369,6 +398,9 @@ def main():
     if not args.no_ess:
         print("ESS-triggered point", file=sys.stderr, flush=True)
         out["ess"] = ess_point(smc, ctx, spec, N_PARTICLES)
+    if not args.no_ess:
+        print("delayed-sampling CRBD point", file=sys.stderr, flush=True)
+        out["crbd_ds"] = crbd_ds_point(smc, ctx, I, tree, N_PARTICLES)
     if not args.no_seir:
         print("SEIR point", file=sys.stderr, flush=True)
         out["seir"] = seir_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
