@@ -37,14 +37,11 @@ TIPS, TREE_SEED, N_PARTICLES = 256, 3000, 1 << 20
 # Algorithmic bytes per launch (FP32 state: lambda, mu), per particle unless noted.
 #  propagate:  anc 4 + gathered block 1 + gathered state 8 read; block 1 + state 8 + lw 8 written
 #              (round 0 only writes: 17)
-#  deep_fold:  the fold of the per-tile partials: 16 B per 256-particle tile
-#  reduce:     lw 8 read (+ 16 B of partials per 1024-particle tile)
+#  reduce:     lw 8 read (+ 16 B of tile sums written per 1024-particle tile)
 #  scan_anc:   lw 8 read, anc 4 written (the final round only updates log Z)
 def bytes_per_launch(kernel: str, n: int, rounds: int) -> float:
     if kernel == "propagate":
         return n * (17 + 30 * (rounds - 1)) / rounds
-    if kernel == "deep_fold":
-        return n / 256 * 16
     if kernel == "reduce":
         return n * 8.0 + n / 1024 * 16
     return n * 12.0 * (rounds - 1) / rounds

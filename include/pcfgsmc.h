@@ -221,10 +221,11 @@ smc_status smc_run_destroy(smc_run* run); /* NULL-safe */
 
 /* Per-kernel timing with HIP events recorded on the context stream around
  * every launch a run makes while profiling is on (smc_step, smc_resample,
- * smc_run_to_end). Index 0 = propagation, 1 = deep-stack pass + fold of the
- * propagation partials, 2 = reduction + fold (log Z, tile offsets), 3 = scan
- * and ancestors; ms = summed durations, launches = count. smc_profile(run, 1)
- * clears previous records; both calls synchronise. */
+ * smc_run_to_end). Index 0 = propagation (with the deep-stack recomputation),
+ * 1 = unused, 2 = reduction (+ the fold of the tile sums for runs above 2^20
+ * particles), 3 = scan and ancestors (log Z, next round); ms = summed
+ * durations, launches = count. smc_profile(run, 1) clears previous records;
+ * both calls synchronise. */
 typedef struct {
     double ms[4];
     uint64_t launches[4];

@@ -170,7 +170,7 @@ size_t real_bytes(const smc_model* m) { return m->precision == 32 ? 4 : 8; }
 void set_prop_tiles(RunDev& h)
 {
     h.prop_tiles = (uint32_t)((h.n + kPropThreads - 1) / kPropThreads);
-    h.fused = h.prop_tiles <= kMaxFusedPropTiles ? 1u : 0u;
+    h.fused = h.red_tiles <= kMaxFusedRedTiles ? 1u : 0u;
 }
 
 smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
@@ -198,9 +198,7 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     h.anc = (uint32_t*)get(n * 4);
     set_prop_tiles(h);
     if (m->kind == SMC_MODEL_CLADS) h.side_stack = get((size_t)kMaxDepthCap * n * 17);
-    h.part_key = (unsigned long long*)get(h.prop_tiles * 8);
-    h.part_cnt = (uint32_t*)get(h.prop_tiles * 4);
-    h.part_steps = (uint32_t*)get(h.prop_tiles * 4);
+    h.groups = (GroupPartials*)get(sizeof(GroupPartials));
     h.part_q = (double*)get(h.red_tiles * 8);
     h.part_e = (double*)get(h.red_tiles * 8);
     h.prefix = (double*)get(h.red_tiles * 8);
@@ -209,7 +207,7 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     r->dev = (RunDev*)get(sizeof(RunDev));
     r->n_prop = h.prop_tiles;
     r->n_red = h.red_tiles;
-    bool ok = h.ctl && h.lw && h.anc && h.part_q && h.part_key && h.part_cnt && h.part_steps &&
+    bool ok = h.ctl && h.lw && h.anc && h.part_q && h.groups &&
               (h.side_stack || m->kind != SMC_MODEL_CLADS) && h.part_e && h.prefix && r->dev &&
               (h.part_q2 || !h.ess_t);
     for (int b = 0; b < 2; ++b) {
@@ -234,20 +232,15 @@ smc_status do_step(smc_run* r)
     if (r->known_status != SMC_OK) return r->known_status;
     hipStream_t st = r->ctx->stream;
     const int kind = r->model->kind, prec = r->model->precision;
-    const bool fused = r->host.fused != 0;
     if (r->profiling) {
-        hipEvent_t a = r->next_event(), b = r->next_event(), c = r->next_event();
-        if (!a || !b || !c) return fail(SMC_ERR_DEVICE, "event creation failed");
+        hipEvent_t a = r->next_event(), b = r->next_event();
+        if (!a || !b) return fail(SMC_ERR_DEVICE, "event creation failed");
         HIP_TRY(hipEventRecord(a, st));
         HIP_TRY(launch_propagate_one(kind, prec, r->host, st));
         HIP_TRY(hipEventRecord(b, st));
-        if (!fused) HIP_TRY(launch_fold_max(r->dev, 1, st));
-        HIP_TRY(hipEventRecord(c, st));
         r->timed.push_back(smc_run::Timed{0, a, b});
-        if (!fused) r->timed.push_back(smc_run::Timed{1, b, c});
     } else {
         HIP_TRY(launch_propagate_one(kind, prec, r->host, st));
-        if (!fused) HIP_TRY(launch_fold_max(r->dev, 1, st));
     }
     r->expect_step = false;
     return SMC_OK;
@@ -496,9 +489,7 @@ static smc_status capture_run(smc_run* r, uint32_t rounds)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     for (uint32_t k = 0; k < rounds && e == hipSuccess; ++k) {
-        const bool fused = r->host.fused != 0;
         e = launch_propagate_one(r->model->kind, r->model->precision, r->host, cap);
-        if (e == hipSuccess && !fused) e = launch_fold_max(r->dev, 1, cap);
         if (e == hipSuccess) e = launch_resample_one(r->host, r->dev, cap, 3);
     }
     hipError_t e2 = hipStreamEndCapture(cap, &g);
@@ -715,16 +706,14 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     h.lw = const_cast<double*>(lw);
     h.anc = anc;
     h.ctl = (RunCtl*)arena.get(sizeof(RunCtl));
-    h.part_key = (unsigned long long*)arena.get(h.prop_tiles * 8);
-    h.part_cnt = (uint32_t*)arena.get(h.prop_tiles * 4);
-    h.part_steps = (uint32_t*)arena.get(h.prop_tiles * 4);
+    h.groups = (GroupPartials*)arena.get(sizeof(GroupPartials));
     h.part_q = (double*)arena.get(h.red_tiles * 8);
     h.part_e = (double*)arena.get(h.red_tiles * 8);
     h.prefix = (double*)arena.get(h.red_tiles * 8);
     RunDev* dev = (RunDev*)arena.get(sizeof(RunDev));
     TileRef* tiles = (TileRef*)arena.get(sizeof(TileRef) * h.red_tiles);
     TileRef* ptiles = (TileRef*)arena.get(sizeof(TileRef) * h.prop_tiles);
-    if (!h.ctl || !h.part_key || !h.part_cnt || !h.part_steps || !h.part_q || !h.part_e || !h.prefix || !dev ||
+    if (!h.ctl || !h.groups || !h.part_q || !h.part_e || !h.prefix || !dev ||
         !tiles || !ptiles) {
         arena.release_all();
         return fail(SMC_ERR_OOM, "device allocation failed");
@@ -740,8 +729,8 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     if (e == hipSuccess) e = hipMemcpyAsync(dev, &h, sizeof(RunDev), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(tiles, th.data(), sizeof(TileRef) * th.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(ptiles, ph.data(), sizeof(TileRef) * ph.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(h.groups, 0, sizeof(GroupPartials), st);
     if (e == hipSuccess) e = launch_maxkey(dev, ptiles, h.prop_tiles, st);
-    if (e == hipSuccess && !h.fused) e = launch_fold_max(dev, 1, st);
     if (e == hipSuccess) e = launch_reduce(dev, tiles, h.red_tiles, 1, !h.fused, st);
     if (e == hipSuccess) e = launch_scan_anc(dev, tiles, h.red_tiles, st);
     if (e == hipSuccess) e = hipMemcpyAsync(logz_inc, &h.ctl->log_z, sizeof(double), hipMemcpyDeviceToDevice, st);
@@ -878,7 +867,6 @@ smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
     for (int32_t k = 0; k < rounds; ++k) {
         for (const auto& g : b->groups) HIP_TRY(launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, st));
         const uint32_t n_runs = (uint32_t)b->runs_h.size();
-        if (b->any_unfused) HIP_TRY(launch_fold_max(b->runs, n_runs, st));
         HIP_TRY(launch_reduce(b->runs, b->red_tiles, b->n_red, n_runs, b->any_unfused, st));
         HIP_TRY(launch_scan_anc(b->runs, b->red_tiles, b->n_red, st));
     }

@@ -46,22 +46,31 @@ struct RunDev {
     double* lw;
     uint32_t* anc;
     void* side_stack;              // ClaDS: per-slot side-lineage stacks (start, rate: FP64; depth: byte)
-    unsigned long long* part_key;  // per propagation tile: max key
-    uint32_t* part_cnt;            // per propagation tile: active count | bad << 31
-    uint32_t* part_steps;          // per propagation tile: block steps
+    struct GroupPartials* groups;  // the propagation's partials, folded into kPartialGroups slots
     double* part_q;                // per reduction tile: sum of grid units
     double* part_e;                // per reduction tile: sum of exp(lw - M)
     unsigned long long* part_q2;   // per reduction tile: sum of squared grid units (lo, hi), ESS rule only
     double* prefix;                // per reduction tile: grid units before the tile (fold-kernel path)
 };
 
-constexpr int kPropThreads = 256;  // one particle per lane
+constexpr int kPropThreads = 128;  // one particle per lane
 constexpr int kRedThreads = 256;
 constexpr int kRedItems = 4;
 constexpr int kTileRed = kRedThreads * kRedItems;  // particles per reduction tile
-// Runs with at most this many propagation tiles fold partials inside the
-// reduction and scan kernels; larger runs use the one-work-group fold kernels.
-constexpr uint32_t kMaxFusedPropTiles = 4096;
+// Runs with at most this many reduction tiles (2^20 particles) fold the
+// reduction's tile sums inside the scan kernel; larger runs use the
+// one-work-group fold kernel.
+constexpr uint32_t kMaxFusedRedTiles = 1024;
+
+// Propagation work-group t folds its partial (max order-key of lw; active
+// count and block steps packed in one word) into slot t mod kPartialGroups
+// with two device-scope atomics on distinct addresses; the reduction reads
+// all slots and the scan clears them for the next round.
+constexpr uint32_t kPartialGroups = 256;
+struct GroupPartials {
+    unsigned long long key[kPartialGroups];     // max order-key (all ones: a NaN or +inf weight)
+    unsigned long long counts[kPartialGroups];  // particles not at b_stop | block executions << 32
+};
 
 // Work-group -> (run index, tile index within the run).
 struct TileRef {

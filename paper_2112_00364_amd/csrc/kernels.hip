@@ -6,20 +6,23 @@
 //                its (block, state) from the ancestor chosen by the previous
 //                resampling (the duplication step of Sec. 3.3, done on read),
 //                runs blocks until a checkpoint or b_stop and writes block,
-//                state and log-weight; each work-group stores its partial
-//                (max log-weight key, active count, NaN flag, block steps).
-//   k_reduce     folds the propagation partials of its run (M = max lw), then
+//                state and log-weight; each work-group folds its partial (max
+//                log-weight key, active count, block steps) into one of
+//                kPartialGroups slots of its run with two device atomics on
+//                distinct addresses.
+//   k_reduce     reads its run's group slots (M = max lw, NaN flag), then
 //                sums exp(lw - M) (for log Z) and the grid-quantised weights of
-//                its tile; tile 0 publishes M and the round's offset word.
+//                its tile; tile 0 publishes M, the counts and the round's
+//                offset word.
 //   k_scan_anc   folds the tile sums of its run (total mass, tile offset),
 //                scans the quantised weights inside the tile exactly, turns
 //                cumulative mass into offspring counts by integer comparison
 //                and writes the ancestor of every output slot it owns
 //                (systematic resampling, Sec. 3.3); tile 0 updates log Z,
 //                decides termination and advances the round.
-// Runs above kMaxFusedPropTiles propagation tiles fold their partials in two
-// one-work-group kernels (k_fold_max, k_fold_sums) instead. No kernel uses
-// same-address atomics: partials are plain stores folded in a fixed order.
+// Runs above kMaxFusedRedTiles reduction tiles fold the tile sums in a
+// one-work-group kernel (k_fold_sums) instead. Sums that decide anything are
+// exact (integers, or maxima), so no result depends on the order of atomics.
 // Memory is structure-of-arrays (Sec. 3.3): consecutive lanes touch
 // consecutive elements of each field.
 #include <type_traits>
@@ -214,32 +217,6 @@ __device__ inline U128 wave_sum(U128 v)
 // order_key of a non-NaN double, so a max over tile keys flags the round.
 constexpr unsigned long long kBadKey = ~0ull;
 
-// Max over a run's propagation tile keys (every thread gets the result). All
-// of a thread's loads are issued before any is used (at most
-// kMaxFusedPropTiles / kThreads of them), so the fold costs one memory latency.
-template <int kThreads>
-__device__ inline unsigned long long fold_prop_keys(const RunDev& R)
-{
-    constexpr int kPer = (int)(kMaxFusedPropTiles / kThreads);
-    unsigned long long v[kPer];
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const uint32_t t = threadIdx.x + (uint32_t)i * kThreads;
-        v[i] = t < R.prop_tiles ? R.part_key[t] : 0ull;
-    }
-    unsigned long long key = 0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) key = v[i] > key ? v[i] : key;
-    key = wave_max_u64(key);
-    __shared__ unsigned long long s_key[kThreads / 64];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) s_key[wave] = key;
-    __syncthreads();
-    unsigned long long r = 0;
-    for (int w = 0; w < kThreads / 64; ++w) r = s_key[w] > r ? s_key[w] : r;
-    return r;
-}
-
 // Partial of a set of particles: max key, active count, NaN flag, block steps.
 struct Partial {
     unsigned long long key;
@@ -274,6 +251,47 @@ __device__ inline Partial block_partial(Partial p)
     return r;
 }
 
+// Folds a work-group's partial into its group slot (device-scope atomics on
+// distinct addresses; work-groups finish spread over the launch, so the slots
+// see little contention).
+__device__ inline void publish_group(const RunDev& R, uint32_t tile, const Partial& r)
+{
+    GroupPartials* g = R.groups;
+    const uint32_t slot = tile & (kPartialGroups - 1u);
+    const unsigned long long key = r.bad ? kBadKey : r.key;
+    const unsigned long long counts = (unsigned long long)r.act | ((unsigned long long)r.steps << 32);
+    if (key) atomicMax(&g->key[slot], key);
+    if (counts) atomicAdd(&g->counts[slot], counts);
+}
+
+// The propagation's partials of a run from its group slots: each wavefront
+// reads all kPartialGroups of them (kPartialGroups / 64 per lane, loads
+// issued together); every thread gets the result. Counts are exact integer
+// sums (a run's active particles and block steps per round stay below 2^32).
+__device__ inline Partial fold_groups(const RunDev& R)
+{
+    constexpr int kPer = (int)(kPartialGroups / 64);
+    static_assert(kPartialGroups % 64 == 0, "whole wavefronts of slots");
+    const GroupPartials* g = R.groups;
+    const int lane = threadIdx.x & 63;
+    unsigned long long kv[kPer], cv[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        kv[i] = g->key[lane + 64 * i];
+        cv[i] = g->counts[lane + 64 * i];
+    }
+    unsigned long long key = 0, counts = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        key = kv[i] > key ? kv[i] : key;
+        counts += cv[i];
+    }
+    key = wave_max_u64(key);
+    const uint32_t act = wave_sum((uint32_t)counts);
+    const uint32_t steps = wave_sum((uint32_t)(counts >> 32));
+    return Partial{key, act, key == kBadKey ? 1u : 0u, steps};
+}
+
 // Work-group partial with no closing barrier: each wavefront leaves its
 // partial in LDS and counts itself in; the last to arrive combines the
 // partials in wavefront order and writes the tile's record. Wavefronts that
@@ -292,33 +310,7 @@ __device__ inline void publish_tile_partial(const RunDev& R, uint32_t tile, Part
     __threadfence_block();
     Partial r = s_part[0];
     for (int w = 1; w < kThreads / 64; ++w) r = combine(r, s_part[w]);
-    R.part_key[tile] = r.bad ? kBadKey : r.key;
-    R.part_cnt[tile] = r.act | (r.bad << 31);
-    R.part_steps[tile] = r.steps;
-}
-
-// Fold a run's propagation partials (every thread of the work-group gets the
-// result); loads are issued in batches of kBatch independent requests.
-template <int kThreads>
-__device__ inline Partial fold_prop_partials(const RunDev& R)
-{
-    constexpr int kBatch = 8;
-    Partial p{0ull, 0u, 0u, 0u};
-    for (uint32_t base = threadIdx.x; base < R.prop_tiles; base += kBatch * kThreads) {
-        unsigned long long kv[kBatch];
-        uint32_t cv[kBatch], sv[kBatch];
-#pragma unroll
-        for (int i = 0; i < kBatch; ++i) {
-            const uint32_t t = base + (uint32_t)i * kThreads;
-            const bool in = t < R.prop_tiles;
-            kv[i] = in ? R.part_key[t] : 0ull;
-            cv[i] = in ? R.part_cnt[t] : 0u;
-            sv[i] = in ? R.part_steps[t] : 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < kBatch; ++i) p = combine(p, Partial{kv[i], cv[i] & 0x7fffffffu, cv[i] >> 31, sv[i]});
-    }
-    return block_partial<kThreads>(p);
+    publish_group(R, tile, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -563,21 +555,10 @@ __device__ __forceinline__ void reduce_body(const RunDev& R, const TileRef tr)
     const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
 #pragma unroll
     for (int k = 0; k < kRedItems; ++k) x[k] = base + k < R.n ? R.lw[base + k] : 0.0;
-    unsigned long long key = 0;
-    Partial f{0ull, 0u, 0u, 0u};
-    if (R.fused) {
-        if (tr.tile == 0) f = fold_prop_partials<kRedThreads>(R);
-        else key = fold_prop_keys<kRedThreads>(R);
-    }
+    const Partial f = fold_groups(R);
     if (status != 0) return;  // uniform over the work-group
-    if (R.fused) {
-        if (tr.tile == 0) {
-            if (threadIdx.x == 0) publish_fold(R, ctl, f);
-            key = f.bad ? kBadKey : f.key;
-        }
-    } else {
-        key = uniform_u32(ctl->bad) ? kBadKey : uniform_u64(ctl->maxkey);
-    }
+    if (tr.tile == 0 && threadIdx.x == 0) publish_fold(R, ctl, f);
+    const unsigned long long key = f.key;
     const double M = key_value(key);
     if (key == kBadKey || key == 0 || M == -__builtin_huge_val()) return;  // uniform over the work-group
     const double scale = (double)(1ull << grid_bits(R.n));
@@ -661,16 +642,8 @@ __device__ inline void finish_round(const RunDev& R, RunCtl* ctl, bool bad, bool
     }
 }
 
-// Fold-kernel path (large runs): one work-group per run.
-__global__ __launch_bounds__(kFoldThreads) void k_fold_max(const RunDev* __restrict__ runs)
-{
-    const RunDev& R = runs[blockIdx.x];
-    RunCtl* ctl = R.ctl;
-    if (ctl->status != 0 || R.fused) return;
-    const Partial f = fold_prop_partials<kFoldThreads>(R);
-    if (threadIdx.x == 0) publish_fold(R, ctl, f);
-}
-
+// Fold-kernel path (large runs): one work-group per run folds the reduction's
+// tile sums and writes the tile offsets.
 __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __restrict__ runs)
 {
     const RunDev& R = runs[blockIdx.x];
@@ -759,7 +732,7 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     double x[kRedItems];
 #pragma unroll
     for (int k = 0; k < kRedItems; ++k) x[k] = first + k < N ? R.lw[first + k] : 0.0;
-    constexpr int kPer = (int)(kMaxFusedPropTiles * kPropThreads / kTileRed / kRedThreads);
+    constexpr int kPer = (int)(kMaxFusedRedTiles / kRedThreads);
     double qv[kPer], ev[kPer];
     U128 q2v[kPer];
     if (R.fused) {
@@ -774,6 +747,13 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     }
 
     if (status != 0) return;  // uniform over the work-group
+    // The propagation partials of this round have been read (by the
+    // reduction): clear the group slots for the next round.
+    if (tr.tile == 0)
+        for (uint32_t i = threadIdx.x; i < kPartialGroups; i += kRedThreads) {
+            R.groups->key[i] = 0ull;
+            R.groups->counts[i] = 0ull;
+        }
     const double M = key_value(key);
     const bool usable = !bad && key != 0 && M != -__builtin_huge_val();
 
@@ -923,11 +903,7 @@ __global__ __launch_bounds__(kPropThreads) void k_maxkey(const RunDev* __restric
         p.act = 1;  // standalone resampling always resamples
     }
     const Partial r = block_partial<kPropThreads>(p);
-    if (threadIdx.x == 0) {
-        R.part_key[tr.tile] = r.bad ? kBadKey : r.key;
-        R.part_cnt[tr.tile] = r.act | (r.bad << 31);
-        R.part_steps[tr.tile] = 0;
-    }
+    if (threadIdx.x == 0) publish_group(R, tr.tile, r);
 }
 
 // Gathered copy of one array: dst[j] = src[anc[j]] for `levels` level-major rows.
@@ -1008,7 +984,12 @@ __global__ void k_selftest_philox(const uint32_t* __restrict__ ctr, const uint32
 // (A kernel rather than a memset so that it can sit inside a captured graph.)
 __global__ void k_reset(RunDev* run, uint64_t seed)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (blockIdx.x != 0) return;
+    for (uint32_t i = threadIdx.x; i < kPartialGroups; i += blockDim.x) {
+        run->groups->key[i] = 0ull;
+        run->groups->counts[i] = 0ull;
+    }
+    if (threadIdx.x != 0) return;
     RunCtl* c = run->ctl;
     c->seed = seed;
     c->maxkey = 0;
@@ -1093,13 +1074,6 @@ hipError_t launch_resample_one(const RunDev& run, const RunDev* run_dev, hipStre
         if (!run.fused) hipLaunchKernelGGL(k_fold_sums, dim3(1), dim3(kFoldThreads), 0, st, run_dev);
     }
     if (part & 2) hipLaunchKernelGGL(k_scan_anc_one, dim3(run.red_tiles), dim3(kRedThreads), 0, st, run);
-    return hipGetLastError();
-}
-
-hipError_t launch_fold_max(const RunDev* runs, uint32_t n_runs, hipStream_t st)
-{
-    if (n_runs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fold_max, dim3(n_runs), dim3(kFoldThreads), 0, st, runs);
     return hipGetLastError();
 }
 

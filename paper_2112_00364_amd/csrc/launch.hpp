@@ -9,7 +9,6 @@ namespace pcfg {
 
 hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const TileRef* tiles, uint32_t n_tiles,
                             hipStream_t st);
-hipError_t launch_fold_max(const RunDev* runs, uint32_t n_runs, hipStream_t st);
 // single run: the run record travels as a kernel argument
 hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipStream_t st);
 hipError_t launch_resample_one(const RunDev& run, const RunDev* run_dev, hipStream_t st, int part);

@@ -29,8 +29,7 @@ import sqlite3
 # Kernel-name prefixes -> the names bench.py reports.
 KERNELS = {
     "k_propagate": "propagate",
-    "k_fold_max": "deep_fold",
-    "k_fold_sums": "deep_fold",
+    "k_fold_sums": "fold_sums",
     "k_reduce": "reduce",
     "k_scan_anc": "scan_anc",
 }

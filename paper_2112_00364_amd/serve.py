@@ -24,16 +24,16 @@ from . import smc
 
 def footprint_bytes(kind: str, n: int, precision: int, stack_depth: int = 0) -> int:
     """Device bytes of one run: double-buffered block + state (+ ClaDS rate
-    stack), log-weights, ancestors, tile partials (+ ClaDS side-lineage stacks:
-    32 levels of 17 bytes per particle)."""
+    stack), log-weights, ancestors, the propagation's group slots and the
+    reduction's tile sums (+ ClaDS side-lineage stacks: 32 levels of 17 bytes
+    per particle)."""
     real = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 4, "seir": 6}[kind]
     ints = {"geometric": 1, "seir": 9}.get(kind, 0)
     rb = 4 if precision == 32 else 8
     per = 2 * (1 + real * rb + 4 * ints + (stack_depth * rb if kind == "clads" else 0)) + 8 + 4
     if kind == "clads":
         per += 32 * 17
-    tiles = (n + 255) // 256
-    return n * per + tiles * 16 + (n + 1023) // 1024 * 24 + 512
+    return n * per + 1024 + (n + 1023) // 1024 * 24 + 512
 
 
 def clads_stack_depth(tree) -> int:

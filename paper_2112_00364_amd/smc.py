@@ -280,7 +280,7 @@ class Run:
         """{kernel: (total ms, launches)} for propagate, deep+fold_max, reduce+fold_sums, scan_anc."""
         t = _KernelTimes()
         _check(lib().smc_profile_read(self._h, C.byref(t)))
-        names = ("propagate", "deep_fold", "reduce", "scan_anc")
+        names = ("propagate", "unused", "reduce", "scan_anc")
         return {names[i]: (t.ms[i], int(t.launches[i])) for i in range(4)}
 
     def _read(self, what, dtype, count=1):
