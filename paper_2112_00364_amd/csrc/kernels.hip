@@ -166,6 +166,11 @@ struct OpAddU32 {
     template <int C, int M>
     static __device__ inline uint32_t mv(uint32_t v) { return dpp_u32<C, M>(v); }
 };
+struct OpMaxU32 {
+    static __device__ inline uint32_t op(uint32_t a, uint32_t b) { return a > b ? a : b; }
+    template <int C, int M>
+    static __device__ inline uint32_t mv(uint32_t v) { return dpp_u32<C, M>(v); }
+};
 struct OpMaxU64 {
     static __device__ inline unsigned long long op(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
     template <int C, int M>
@@ -841,36 +846,56 @@ __device__ __forceinline__ void scan_anc_body(const RunDev& R, const TileRef tr)
     const uint32_t o0 = s_o0;
     const uint32_t o1 = s_c[count - 1];
     // Output slot jj descends from the first particle of the tile whose
-    // running offspring count exceeds jj. Each thread resolves four slots per
-    // pass with interleaved binary searches of kHalvings steps (count <=
-    // kTileRed <= 2^kHalvings, so that many halvings always suffice).
-    constexpr int kSearch = 4;
-    constexpr int kHalvings = kTileRed <= 1024 ? 10 : (kTileRed <= 2048 ? 11 : (kTileRed <= 4096 ? 12 : 13));
-    static_assert(kTileRed <= 8192, "the search length covers the tile");
-    for (uint32_t b = o0 + threadIdx.x; b < o1; b += kSearch * kRedThreads) {
-        uint32_t lo[kSearch], hi[kSearch];
+    // running offspring count exceeds jj. Each particle with offspring marks
+    // the first slot of its range with its index + 1 in an LDS window of up
+    // to kWindow slots; an inclusive prefix maximum over the window then
+    // gives every slot its ancestor (a slot between two marks belongs to the
+    // last particle that started at or before it), and the window is copied
+    // out with coalesced stores. The work is the same for every thread
+    // whatever the weights. A tile with more slots than the window takes
+    // several windows, each starting from the last ancestor of the previous.
+    constexpr uint32_t kWindow = 4096;
+    __shared__ uint32_t s_win[kWindow + kWindow / 16];
+    __shared__ uint32_t s_segmax[kRedThreads / 64];
+    auto at = [](uint32_t i) { return i + (i >> 4); };  // padding against bank conflicts
+    uint32_t prev = 0;  // ancestor (+ 1) of the slot before the window
+    for (uint32_t w0 = o0; w0 < o1; w0 += kWindow) {
+        const uint32_t len = (o1 - w0) < kWindow ? (o1 - w0) : kWindow;
+        for (uint32_t i = threadIdx.x; i < len; i += kRedThreads) s_win[at(i)] = 0u;
+        __syncthreads();
 #pragma unroll
-        for (int s = 0; s < kSearch; ++s) {
-            lo[s] = 0;
-            hi[s] = count - 1;
-        }
-#pragma unroll
-        for (int it = 0; it < kHalvings; ++it) {
-#pragma unroll
-            for (int s = 0; s < kSearch; ++s) {
-                const uint32_t jj = b + (uint32_t)s * kRedThreads;
-                const bool open = lo[s] < hi[s];
-                const uint32_t mid = (lo[s] + hi[s]) >> 1;
-                const bool right = s_c[mid] <= jj;
-                lo[s] = (open && right) ? mid + 1 : lo[s];
-                hi[s] = (open && !right) ? mid : hi[s];
+        for (int k = 0; k < kRedItems; ++k) {
+            const uint32_t idx = threadIdx.x * kRedItems + (uint32_t)k;
+            if (idx < count) {
+                const uint32_t before = idx == 0 ? o0 : s_c[idx - 1];
+                const uint32_t after = s_c[idx];
+                if (after > before && before >= w0 && before - w0 < len) s_win[at(before - w0)] = idx + 1u;
             }
         }
-#pragma unroll
-        for (int s = 0; s < kSearch; ++s) {
-            const uint32_t jj = b + (uint32_t)s * kRedThreads;
-            if (jj < o1) R.anc[jj] = tile0 + lo[s];
-        }
+        __syncthreads();
+        // thread t scans slots [t seg, (t + 1) seg) of the window
+        const uint32_t seg = (len + kRedThreads - 1) / kRedThreads;
+        const uint32_t s0 = threadIdx.x * seg;
+        uint32_t m = 0;
+        for (uint32_t j = 0; j < seg; ++j)
+            if (s0 + j < len) m = s_win[at(s0 + j)] > m ? s_win[at(s0 + j)] : m;
+        const uint32_t incl = wave_incl_scan<OpMaxU32>(m);
+        if (lane == 63) s_segmax[wave] = incl;
+        __syncthreads();
+        uint32_t run = prev;
+        for (int w = 0; w < wave; ++w) run = s_segmax[w] > run ? s_segmax[w] : run;
+        const uint32_t excl = (uint32_t)__shfl_up((int)incl, 1, 64);
+        if (lane > 0) run = excl > run ? excl : run;
+        for (uint32_t j = 0; j < seg; ++j)
+            if (s0 + j < len) {
+                const uint32_t v = s_win[at(s0 + j)];
+                run = v > run ? v : run;
+                s_win[at(s0 + j)] = run;
+            }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < len; i += kRedThreads) R.anc[w0 + i] = tile0 + s_win[at(i)] - 1u;
+        prev = s_win[at(len - 1)];
+        __syncthreads();  // the window is reused
     }
 }
 
