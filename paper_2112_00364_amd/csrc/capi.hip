@@ -167,9 +167,9 @@ smc_status read_ctl(smc_run* r, RunCtl* out)
 size_t real_bytes(const smc_model* m) { return m->precision == 32 ? 4 : 8; }
 
 // Allocate and initialise a run's device state (Alg. 1 step 1).
-void set_prop_tiles(RunDev& h)
+void set_prop_tiles(RunDev& h, int lanes)
 {
-    h.prop_tiles = (uint32_t)((h.n + kPropThreads - 1) / kPropThreads);
+    h.prop_tiles = (uint32_t)((h.n + lanes - 1) / lanes);
     h.fused = h.red_tiles <= kMaxFusedRedTiles ? 1u : 0u;
 }
 
@@ -196,7 +196,7 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
     }
     h.lw = (double*)get(n * 8);
     h.anc = (uint32_t*)get(n * 4);
-    set_prop_tiles(h);
+    set_prop_tiles(h, prop_threads(m->kind));
     if (m->kind == SMC_MODEL_CLADS) h.side_stack = get((size_t)kMaxDepthCap * n * 17);
     h.groups = (GroupPartials*)get(sizeof(GroupPartials));
     h.part_q = (double*)get(h.red_tiles * 8);
@@ -702,7 +702,7 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     RunDev h{};
     h.n = (uint32_t)n;
     h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
-    set_prop_tiles(h);
+    set_prop_tiles(h, kMaxkeyThreads);
     h.lw = const_cast<double*>(lw);
     h.anc = anc;
     h.ctl = (RunCtl*)arena.get(sizeof(RunCtl));

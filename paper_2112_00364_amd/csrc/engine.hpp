@@ -36,7 +36,7 @@ struct ParticleBuf {
 struct RunDev {
     uint32_t n;
     uint32_t red_tiles;            // reduction / scan tiles of kTileRed particles
-    uint32_t prop_tiles;           // propagation tiles of kPropThreads particles
+    uint32_t prop_tiles;           // propagation tiles of prop_threads(kind) particles
     uint32_t fused;                // 1: the reduction and scan fold the partials themselves
     uint32_t ess_t;                // ESS threshold numerator over 2^16 (0: resample every round)
     uint32_t pad_;
@@ -53,7 +53,12 @@ struct RunDev {
     double* prefix;                // per reduction tile: grid units before the tile (fold-kernel path)
 };
 
-constexpr int kPropThreads = 128;  // one particle per lane
+// Lanes (= particles) per propagation work-group, by model kind: 128 for the
+// tree models and the small ones (finer scheduling of divergent blocks),
+// 256 for the SEIR model (measured faster). The resampling-only entry point
+// takes its maxima over tiles of kMaxkeyThreads.
+__host__ __device__ constexpr int prop_threads(int kind) { return kind == 4 ? 256 : 128; }
+constexpr int kMaxkeyThreads = 256;
 constexpr int kRedThreads = 256;
 constexpr int kRedItems = 4;
 constexpr int kTileRed = kRedThreads * kRedItems;  // particles per reduction tile

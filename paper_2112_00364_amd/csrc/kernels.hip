@@ -471,7 +471,8 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint64_t
 template <int Kind, class Real>
 __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
 {
-    const uint32_t j = tile * kPropThreads + threadIdx.x;
+    constexpr int kThreads = prop_threads(Kind);
+    const uint32_t j = tile * kThreads + threadIdx.x;
     const bool valid = j < R.n;
     RunCtl* ctl = R.ctl;
     const int32_t status = uniform_i32(ctl->status);
@@ -497,7 +498,7 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
     bool deep = false;
     if (valid) deep = !run_particle<Kind, Real, false>(R, m, seed, j, round, src, lw0, blk, lw, steps, nullptr);
     if constexpr (Kind == 2 || Kind == 5) {
-        __shared__ __align__(16) unsigned char s_stack[kPropThreads / 64][kDeepStackBytes];
+        __shared__ __align__(16) unsigned char s_stack[kThreads / 64][kDeepStackBytes];
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
         unsigned long long pending = __ballot(deep);
         while (pending) {
@@ -514,19 +515,19 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
         p.act = blk != kStop ? 1u : 0u;
         p.steps = steps;
     }
-    publish_tile_partial<kPropThreads>(R, tile, p, &s_arrived);
+    publish_tile_partial<kThreads>(R, tile, p, &s_arrived);
 }
 
 // Entry points: one run (its record is a kernel argument, tile = work-group)
 // or a batch (work-group -> (run, tile) table).
 template <int Kind, class Real>
-__global__ __launch_bounds__(kPropThreads) void k_propagate_one(const RunDev R)
+__global__ __launch_bounds__(prop_threads(Kind)) void k_propagate_one(const RunDev R)
 {
     propagate_body<Kind, Real>(R, blockIdx.x);
 }
 
 template <int Kind, class Real>
-__global__ __launch_bounds__(kPropThreads) void k_propagate(const RunDev* __restrict__ runs,
+__global__ __launch_bounds__(prop_threads(Kind)) void k_propagate(const RunDev* __restrict__ runs,
                                                              const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
@@ -914,12 +915,12 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
 // ---------------------------------------------------------------------------
 // Standalone pieces: max of a given weight vector, reads, self-tests, setup.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kPropThreads) void k_maxkey(const RunDev* __restrict__ runs,
+__global__ __launch_bounds__(kMaxkeyThreads) void k_maxkey(const RunDev* __restrict__ runs,
                                                           const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
     const RunDev& R = runs[tr.run];
-    const uint32_t i = tr.tile * kPropThreads + threadIdx.x;
+    const uint32_t i = tr.tile * kMaxkeyThreads + threadIdx.x;
     Partial p{0ull, 0u, 0u, 0u};
     if (i < R.n) {
         const double x = R.lw[i];
@@ -927,7 +928,7 @@ __global__ __launch_bounds__(kPropThreads) void k_maxkey(const RunDev* __restric
         else p.key = order_key(x);
         p.act = 1;  // standalone resampling always resamples
     }
-    const Partial r = block_partial<kPropThreads>(p);
+    const Partial r = block_partial<kMaxkeyThreads>(p);
     if (threadIdx.x == 0) publish_group(R, tr.tile, r);
 }
 
@@ -1059,7 +1060,7 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
                             hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
-    dim3 g(n_tiles), b(kPropThreads);
+    dim3 g(n_tiles), b(prop_threads(kind));
     if (kind == 0) hipLaunchKernelGGL((k_propagate<0, double>), g, b, 0, st, runs, tiles);
     else if (kind == 1 && precision == 32) hipLaunchKernelGGL((k_propagate<1, float>), g, b, 0, st, runs, tiles);
     else if (kind == 1) hipLaunchKernelGGL((k_propagate<1, double>), g, b, 0, st, runs, tiles);
@@ -1076,7 +1077,7 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
 
 hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipStream_t st)
 {
-    dim3 g(run.prop_tiles), b(kPropThreads);
+    dim3 g(run.prop_tiles), b(prop_threads(kind));
     if (kind == 0) hipLaunchKernelGGL((k_propagate_one<0, double>), g, b, 0, st, run);
     else if (kind == 1 && precision == 32) hipLaunchKernelGGL((k_propagate_one<1, float>), g, b, 0, st, run);
     else if (kind == 1) hipLaunchKernelGGL((k_propagate_one<1, double>), g, b, 0, st, run);
@@ -1120,7 +1121,7 @@ hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_
 
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_maxkey, dim3(n_tiles), dim3(kPropThreads), 0, st, runs, tiles);
+    hipLaunchKernelGGL(k_maxkey, dim3(n_tiles), dim3(kMaxkeyThreads), 0, st, runs, tiles);
     return hipGetLastError();
 }
 
