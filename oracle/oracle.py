@@ -68,6 +68,9 @@ def lib():
     L.or_log_factorial.argtypes = [C.c_int64]; L.or_log_factorial.restype = C.c_double
     L.or_log_binomial_pmf.argtypes = [C.c_int64, C.c_int64, C.c_double]; L.or_log_binomial_pmf.restype = C.c_double
     L.or_sample.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_uint64, C.c_int64, f64p]
+    L.or_draw.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, u32p,
+                          C.POINTER(C.c_int32)]
+    L.or_draw.restype = C.c_double
     L.or_ancestors.argtypes = [u64p, C.c_uint64, C.c_uint32, u32p]
     L.or_systematic.argtypes = [f64p, C.c_uint64, C.c_uint64, C.c_uint32, u32p, f64p, u64p]
     L.or_systematic.restype = C.c_int32
@@ -164,6 +167,15 @@ def sample(kind, a, b, seed, count):
     code = {"binomial": 0, "gamma": 1, "beta": 2, "negbin": 3, "lomax": 4}[kind]
     lib().or_sample(code, float(a), float(b), int(seed), int(count), _ptr(out, C.c_double))
     return out
+
+
+def draw(dist, a, b, seed, particle, rnd, k):
+    """One program draw (or_draw): returns (value, next word index, fault flag)."""
+    kk = C.c_uint32(int(k))
+    fault = C.c_int32(0)
+    v = lib().or_draw(int(dist), float(a), float(b), int(seed), int(particle), int(rnd), C.byref(kk),
+                      C.byref(fault))
+    return v, int(kk.value), bool(fault.value)
 
 
 def ess_resamples(lw, threshold):

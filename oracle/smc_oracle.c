@@ -457,6 +457,50 @@ void or_sample(int32_t kind, double a, double b, uint64_t seed, int64_t count, d
     }
 }
 
+/* One draw of a compiled program (Sec. 4) from the stream of particle slot
+ * `particle` in round `round`, starting at word *k (advanced past the words
+ * used). Distributions: 0 uniform(a, b) = a + (b - a) u; 1 normal(mean a,
+ * sd b) = a + b z; 2 exponential(rate a) = -log u / a; 3 gamma(shape a, scale
+ * b) = b g, shape >= 1; 4 beta(a, b), both >= 1; 5 bernoulli(a): 1 if u < a;
+ * 6 poisson(a); 7 binomial(n = a, p = b) with n a count below 2^31 and p in
+ * [0, 1]. *fault = 1 (and 0 returned) when an argument is outside these
+ * ranges or the Poisson mean exceeds the event cap; such a particle takes
+ * weight -inf and stops. */
+double or_draw(int32_t dist, double a, double b, uint64_t seed, uint32_t particle, uint32_t round,
+               uint32_t* k, int32_t* fault)
+{
+    stream s = {seed, particle, round, OR_TAG_PROPAGATE, *k};
+    double v = 0.0;
+    *fault = 0;
+    switch (dist) {
+    case 0: v = uniform_ab(&s, a, b); break;
+    case 1: v = a + b * normal01(&s); break;
+    case 2: v = exponential(&s, a); break;
+    case 3:
+        if (!(a >= 1.0)) { *fault = 1; break; }
+        v = b * gamma_mt(&s, a);
+        break;
+    case 4:
+        if (!(a >= 1.0 && b >= 1.0)) { *fault = 1; break; }
+        v = beta_draw(&s, a, b);
+        break;
+    case 5: v = bernoulli(&s, a) ? 1.0 : 0.0; break;
+    case 6: {
+        int64_t c = poisson(&s, a);
+        if (c < 0) *fault = 1;
+        else v = (double)c;
+        break;
+    }
+    case 7:
+        if (!(a >= 0.0 && a < 2147483648.0 && a == floor(a) && b >= 0.0 && b <= 1.0)) { *fault = 1; break; }
+        v = (double)binomial_draw(&s, (int64_t)a, b);
+        break;
+    default: *fault = 1;
+    }
+    *k = s.k;
+    return *fault ? 0.0 : v;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Particle storage (one array per field, as the paper lays particles out).  */
 /* ------------------------------------------------------------------------- */

@@ -63,6 +63,9 @@ int64_t or_poisson_words(double m, const uint32_t* words, int32_t n_words, int32
 double or_log_factorial(int64_t k);
 double or_log_binomial_pmf(int64_t y, int64_t z, double p);
 void or_sample(int32_t kind, double a, double b, uint64_t seed, int64_t count, double* out);
+/* One draw of a compiled program's sampler from a particle's stream at word *k. */
+double or_draw(int32_t dist, double a, double b, uint64_t seed, uint32_t particle, uint32_t round,
+               uint32_t* k, int32_t* fault);
 
 /* Resampling alone (Alg. 1 step 3) on a given log-weight vector. */
 void or_ancestors(const uint64_t* Q, uint64_t n, uint32_t U, uint32_t* anc);

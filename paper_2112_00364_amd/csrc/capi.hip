@@ -19,6 +19,7 @@
 
 #include "engine.hpp"
 #include "launch.hpp"
+#include "program.hpp"
 
 using namespace pcfg;
 
@@ -95,11 +96,128 @@ int real_fields(int kind)
     default: return 0;
     }
 }
-int stored_int_fields(int kind) { return kind == SMC_MODEL_GEOMETRIC ? 1 : kind == SMC_MODEL_SEIR ? 9 : 0; }
+int stored_int_fields(int kind)
+{
+    return (kind == SMC_MODEL_GEOMETRIC || kind == SMC_MODEL_PROGRAM) ? 1 : kind == SMC_MODEL_SEIR ? 9 : 0;
+}
 // Int fields as the model defines them (cursor-like ones follow the round and
 // are not stored): geometric flips; LGSSM t; CRBD node; ClaDS node and stack
-// size; SEIR nine counts and the day; delayed-sampling CRBD node.
+// size; SEIR nine counts and the day; delayed-sampling CRBD node; a compiled
+// program's stack pointer.
 int logical_int_fields(int kind) { return kind == SMC_MODEL_CLADS ? 2 : kind == SMC_MODEL_SEIR ? 10 : 1; }
+
+// Static checks of a compiled program. Together with the kernel's run-time
+// checks of sp, stored return blocks, return-value locations and data
+// indices they keep every access of the interpreter inside its buffers:
+// registers below kProgRegs; constants, arrays, distributions and blocks in
+// range; frame offsets below the block's frame size; callee-frame stores only
+// between CALLFRAME and its PUSH, with no jump into or out of that stretch
+// (so the capacity check of CALLFRAME precedes them on every path); jumps
+// forward inside the block; every block opened by FRAME and closed by a
+// terminator.
+smc_status check_program(const smc_program_desc* p)
+{
+    auto bad = [](const std::string& m) { return fail(SMC_ERR_INVALID, "program: " + m); };
+    if (!p) return bad("description is NULL");
+    if (p->n_blocks < 1 || p->n_blocks > kProgMaxBlocks) return bad("n_blocks must be in [1, 254]");
+    if (!p->block_start || !p->code) return bad("block_start or code is NULL");
+    if (p->n_code < 1 || p->n_code > kProgMaxCode) return bad("n_code must be in [1, 2^20]");
+    if (p->stack_words < 1 || p->stack_words > kProgMaxStack) return bad("stack_words must be in [1, 4096]");
+    if (p->n_consts > kProgMaxCode || (p->n_consts > 0 && !p->consts)) return bad("constants missing");
+    if (p->n_data > (1u << 26) || (p->n_data > 0 && !p->data)) return bad("data missing");
+    if (p->n_arrays > kProgMaxCode || (p->n_arrays > 0 && !p->array_start)) return bad("array_start missing");
+    if (p->n_arrays > 0) {
+        if (p->array_start[0] != 0 || p->array_start[p->n_arrays] != p->n_data)
+            return bad("array_start must run from 0 to n_data");
+        for (uint32_t a = 0; a < p->n_arrays; ++a)
+            if (p->array_start[a + 1] < p->array_start[a]) return bad("array_start must not decrease");
+    }
+    if (p->block_start[0] != 0 || p->block_start[p->n_blocks] != p->n_code)
+        return bad("block_start must run from 0 to n_code");
+    std::vector<int> open_at;
+    for (uint32_t b = 0; b < p->n_blocks; ++b) {
+        const uint32_t start = p->block_start[b], end = p->block_start[b + 1];
+        const std::string where = "block " + std::to_string(b);
+        if (end <= start) return bad(where + " is empty");
+        open_at.assign(end - start + 1, 0);
+        uint32_t frame = 0;
+        int64_t open = -1;  // words of the callee frame opened by CALLFRAME, -1 = none
+        for (uint32_t pc = start; pc < end; ++pc) {
+            const uint64_t w = p->code[pc];
+            const uint32_t op = (uint32_t)(w & 255u), x = (uint32_t)(w >> 8) & 255u, y = (uint32_t)(w >> 16) & 255u,
+                           z = (uint32_t)(w >> 24) & 255u, imm = (uint32_t)(w >> 32);
+            const std::string at = where + " instruction " + std::to_string(pc) + ": ";
+            open_at[pc - start] = open >= 0 ? 1 : 0;
+            if (op < kOpFrame || op >= kOpCount) return bad(at + "unknown opcode");
+            if (x >= (uint32_t)kProgRegs || y >= (uint32_t)kProgRegs || z >= (uint32_t)kProgRegs)
+                return bad(at + "register out of range");
+            if ((op == kOpFrame) != (pc == start)) return bad(at + "FRAME must open the block, and only there");
+            switch (op) {
+            case kOpFrame:
+                if (imm > p->stack_words) return bad(at + "frame larger than the stack");
+                frame = imm;
+                break;
+            case kOpConst:
+                if (imm >= p->n_consts) return bad(at + "constant out of range");
+                break;
+            case kOpLdf:
+            case kOpStf:
+            case kOpAddr:
+                if (imm >= frame) return bad(at + "frame offset out of range");
+                break;
+            case kOpData:
+            case kOpLen:
+                if (imm >= p->n_arrays) return bad(at + "data array out of range");
+                break;
+            case kOpSample:
+                if (imm >= kDistCount) return bad(at + "unknown distribution");
+                break;
+            case kOpObserve:
+                if (imm >= kDistCount || imm == kDistGamma || imm == kDistBeta)
+                    return bad(at + "distribution cannot be observed");
+                break;
+            case kOpJz:
+            case kOpJmp:
+                if (!(imm > pc && imm < end)) return bad(at + "jump target must lie ahead in the same block");
+                if (open >= 0) return bad(at + "jump inside an open callee frame");
+                break;
+            case kOpCallFrame:
+                if (open >= 0) return bad(at + "callee frame already open");
+                if (imm < 1 || imm > p->stack_words) return bad(at + "callee frame size out of range");
+                open = imm;
+                break;
+            case kOpStn:
+                if (open < 0 || imm >= (uint32_t)open) return bad(at + "STN outside the open callee frame");
+                break;
+            case kOpPush:
+                if (open < 0 || imm != (uint32_t)open) return bad(at + "PUSH must close the open callee frame");
+                open = -1;
+                break;
+            case kOpStret:
+                if (frame < 2) return bad(at + "STRET needs a frame of at least 2 words");
+                break;
+            case kOpJret:
+                if (frame < 2 || imm != frame) return bad(at + "JRET must pop the block's frame");
+                break;
+            case kOpGoto:
+            case kOpCkpt:
+                if (imm >= p->n_blocks) return bad(at + "block out of range");
+                break;
+            default: break;
+            }
+            const bool term = op == kOpGoto || op == kOpCkpt || op == kOpJret || op == kOpFault;
+            if (term && open >= 0) return bad(at + "block transition with an open callee frame");
+            if (pc + 1 == end && !term) return bad(where + " does not end with GOTO, CKPT, JRET or FAULT");
+        }
+        for (uint32_t pc = start; pc < end; ++pc) {
+            const uint64_t w = p->code[pc];
+            const uint32_t op = (uint32_t)(w & 255u), imm = (uint32_t)(w >> 32);
+            if ((op == kOpJz || op == kOpJmp) && open_at[imm - start])
+                return bad(where + " instruction " + std::to_string(pc) + ": jump into an open callee frame");
+        }
+    }
+    return SMC_OK;
+}
 
 }  // namespace
 
@@ -192,7 +310,8 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
         h.buf[b].blk = (uint8_t*)get(n);
         for (int f = 0; f < real_fields(m->kind); ++f) h.buf[b].real[f] = get(n * rb);
         for (int f = 0; f < stored_int_fields(m->kind); ++f) h.buf[b].ints[f] = (int32_t*)get(n * 4);
-        if (m->kind == SMC_MODEL_CLADS) h.buf[b].stack = get(n * rb * (size_t)m->stack_depth);
+        if (m->kind == SMC_MODEL_CLADS || m->kind == SMC_MODEL_PROGRAM)
+            h.buf[b].stack = get(n * rb * (size_t)m->stack_depth);
     }
     h.lw = (double*)get(n * 8);
     h.anc = (uint32_t*)get(n * 4);
@@ -214,7 +333,7 @@ smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
         ok = ok && h.buf[b].blk;
         for (int f = 0; f < real_fields(m->kind); ++f) ok = ok && h.buf[b].real[f];
         for (int f = 0; f < stored_int_fields(m->kind); ++f) ok = ok && h.buf[b].ints[f];
-        if (m->kind == SMC_MODEL_CLADS) ok = ok && h.buf[b].stack;
+        if (m->kind == SMC_MODEL_CLADS || m->kind == SMC_MODEL_PROGRAM) ok = ok && h.buf[b].stack;
     }
     if (!ok) {
         r->arena.release_all();
@@ -288,6 +407,8 @@ extern "C" {
 const char* smc_last_error(void) { return g_error.c_str(); }
 const char* smc_version(void) { return "pcfgsmc 0.1 gfx950"; }
 
+smc_status smc_program_check(const smc_program_desc* program) { return check_program(program); }
+
 smc_status smc_ctx_create(int32_t device, void* stream, const smc_allocator* allocator, smc_ctx** out)
 {
     if (!out) return fail(SMC_ERR_INVALID, "out is NULL");
@@ -320,8 +441,13 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
 {
     if (!ctx || !d || !out) return fail(SMC_ERR_INVALID, "NULL argument");
     *out = nullptr;
-    if (d->kind < SMC_MODEL_GEOMETRIC || d->kind > SMC_MODEL_CRBD_DS) return fail(SMC_ERR_INVALID, "unknown model kind");
+    if (d->kind < SMC_MODEL_GEOMETRIC || d->kind > SMC_MODEL_PROGRAM) return fail(SMC_ERR_INVALID, "unknown model kind");
     if (d->precision != 32 && d->precision != 64) return fail(SMC_ERR_INVALID, "precision must be 32 or 64");
+    if (d->kind == SMC_MODEL_PROGRAM) {
+        if (d->precision != 64) return fail(SMC_ERR_INVALID, "compiled programs keep FP64 state: precision must be 64");
+        const smc_status s = check_program(d->program);
+        if (s != SMC_OK) return s;
+    }
     const bool tree = d->kind == SMC_MODEL_CRBD || d->kind == SMC_MODEL_CLADS || d->kind == SMC_MODEL_CRBD_DS;
     if (tree) {
         if (d->n_nodes < 1 || d->n_nodes > 1 << 20 || !d->parent || !d->left || !d->age)
@@ -403,6 +529,25 @@ smc_status smc_model_register(smc_ctx* ctx, const smc_model_desc* d, smc_model**
     if (d->kind == SMC_MODEL_LGSSM || d->kind == SMC_MODEL_SEIR) {
         h.y = (const double*)upload(d->y, sizeof(double) * d->T);
         ok = ok && h.y;
+    }
+    if (d->kind == SMC_MODEL_PROGRAM) {
+        const smc_program_desc* p = d->program;
+        static const double zero = 0.0;  // placeholders for empty tables (outlive the async copies)
+        static const uint32_t start0 = 0;
+        ProgramDev& g = h.prog;
+        g.code = (const unsigned long long*)upload(p->code, sizeof(uint64_t) * p->n_code);
+        g.block_start = (const uint32_t*)upload(p->block_start, sizeof(uint32_t) * (p->n_blocks + 1));
+        g.consts = (const double*)(p->n_consts ? upload(p->consts, sizeof(double) * p->n_consts) : upload(&zero, 8));
+        g.data = (const double*)(p->n_data ? upload(p->data, sizeof(double) * p->n_data) : upload(&zero, 8));
+        g.array_start = (const uint32_t*)(p->n_arrays ? upload(p->array_start, sizeof(uint32_t) * (p->n_arrays + 1))
+                                                      : upload(&start0, 4));
+        g.n_blocks = p->n_blocks;
+        g.n_arrays = p->n_arrays;
+        g.stack_words = p->stack_words;
+        g.n_consts = p->n_consts;
+        m->stack_depth = (int)p->stack_words;
+        h.stack_depth = m->stack_depth;
+        ok = ok && g.code && g.block_start && g.consts && g.data && g.array_start;
     }
     m->dev = (ModelDev*)m->arena.get(sizeof(ModelDev));
     ok = ok && m->dev;
@@ -626,7 +771,7 @@ smc_status smc_read(smc_run* r, int32_t what, void* dst, size_t bytes)
         return SMC_OK;
     }
     f -= logical_int_fields(m->kind);
-    if (f == 0 && m->kind == SMC_MODEL_CLADS) {
+    if (f == 0 && (m->kind == SMC_MODEL_CLADS || m->kind == SMC_MODEL_PROGRAM)) {
         const uint64_t depth = (uint64_t)m->stack_depth;
         const size_t need = (size_t)elem * n * depth;
         if (bytes < need) return fail(SMC_ERR_INVALID, "destination too small");

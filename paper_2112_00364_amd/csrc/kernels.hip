@@ -29,6 +29,7 @@
 
 #include "engine.hpp"
 #include "launch.hpp"
+#include "program.hpp"
 
 namespace pcfg {
 
@@ -212,6 +213,7 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v)
 {
     return lane63_u64(wave_incl_scan<OpMaxU64>(v));
 }
+__device__ inline uint32_t wave_min_u32(uint32_t v) { return ~lane63_u32(wave_incl_scan<OpMaxU32>(~v)); }
 __device__ inline U128 wave_sum(U128 v)
 {
     v = wave_incl_scan<OpAddU128>(v);
@@ -464,12 +466,196 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint64_t
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Compiled programs (Sec. 4): each lane interprets the bytecode blocks of its
+// particle until a checkpoint or b_stop. The particle's state is its block,
+// its stack pointer sp and a stack of FP64 words stored level-major (word w
+// of slot j at w * N + j), so lanes touching the same word touch consecutive
+// addresses. The gather of the previous resampling copies only the live part
+// [0, sp) of the ancestor's stack (Sec. 3.3).
+//
+// Scheduling: every step executes the instruction at the smallest program
+// counter among the wavefront's running lanes, for the lanes at that counter.
+// Opcode and operands are then wavefront-uniform (one scalar load, scalar
+// branches, LDS register addresses off a scalar offset), and since jumps
+// inside a block only go forward, lanes split by a branch rejoin where the
+// branches meet. Registers live in LDS (lane-interleaved: no bank conflicts).
+// Every stack and data access is in range by construction: the host checks
+// operand bounds, frame sizes and jump targets; the kernel checks sp against
+// frame sizes and the capacity, and the stored return blocks, return-value
+// locations and data indices, faulting the particle (weight -inf) otherwise.
+// ---------------------------------------------------------------------------
+template <int kThreads>
+__device__ __forceinline__ void program_body(const RunDev& R, uint32_t tile)
+{
+    const uint32_t j = tile * kThreads + threadIdx.x;
+    const bool valid = j < R.n;
+    RunCtl* ctl = R.ctl;
+    const int32_t status = uniform_i32(ctl->status);
+    const uint32_t round = uniform_u32(ctl->round);
+    const uint64_t seed = uniform_u64(ctl->seed);
+    const bool carry = uniform_u32(ctl->carry) != 0;
+    const uint32_t ancestor = valid ? R.anc[j] : 0u;
+    if (status != 0) return;  // uniform over the work-group
+    const uint32_t src = (round > 0 && !carry) ? ancestor : j;
+    const double lw0 = (carry && valid) ? R.lw[j] : 0.0;
+    __shared__ uint32_t s_arrived;
+    __shared__ double s_reg[kProgRegs * kThreads];
+    if (threadIdx.x == 0) s_arrived = 0;
+    __syncthreads();
+    const ProgramDev P = R.model->prog;
+    const ParticleBuf& out = R.buf[round & 1u];
+    const ParticleBuf& in = R.buf[(round & 1u) ^ 1u];
+    const uint64_t n = R.n;
+    double* __restrict__ st = static_cast<double*>(out.stack);
+    const double* __restrict__ st_in = static_cast<const double*>(in.stack);
+    double* __restrict__ reg = s_reg + threadIdx.x;  // register r at reg[r * kThreads]
+
+    uint32_t blk = kStop, sp = 0;
+    double lw = lw0;
+    if (valid) {
+        blk = round > 0 ? in.blk[src] : 0u;
+        sp = round > 0 ? (uint32_t)in.ints[0][src] : 0u;
+    }
+    if (sp > P.stack_words) {  // never written by this kernel; keeps every access in range
+        sp = 0;
+        blk = kStop;
+        lw = -__builtin_huge_val();
+    }
+    for (uint32_t w = 0; w < sp; ++w) st[w * n + j] = st_in[w * n + src];
+
+    bool live = valid && blk != kStop;
+    uint32_t pc = live ? P.block_start[blk] : 0u;
+    uint32_t fp = 0, steps = live ? 1u : 0u, executed = 0;
+    Stream s;
+    s.start(seed, j, round, kTagPropagate);
+    for (;;) {
+        const uint32_t sel = wave_min_u32(live ? pc : 0xffffffffu);
+        if (sel == 0xffffffffu) break;  // uniform: no lane of the wavefront is running
+        if (!(live && pc == sel)) continue;
+        const unsigned long long word = P.code[sel];
+        const uint32_t lo = (uint32_t)word;
+        const uint32_t op = lo & 255u, x = (lo >> 8) & 255u, y = (lo >> 16) & 255u, z = lo >> 24;
+        const uint32_t imm = (uint32_t)(word >> 32);
+        double* rx = reg + x * kThreads;
+        const double ry = reg[y * kThreads], rz = reg[z * kThreads];
+        pc = sel + 1;
+        bool fault = ++executed > kProgInstrBudget;
+        if (!fault) {
+            switch (op) {
+            case kOpFrame:
+                if (sp < imm) fault = true;
+                else fp = sp - imm;
+                break;
+            case kOpConst: *rx = P.consts[imm]; break;
+            case kOpImm: *rx = (double)(int32_t)imm; break;
+            case kOpMov: *rx = ry; break;
+            case kOpLdf: *rx = st[(uint64_t)(fp + imm) * n + j]; break;
+            case kOpStf: st[(uint64_t)(fp + imm) * n + j] = *rx; break;
+            case kOpAdd: *rx = ry + rz; break;
+            case kOpSub: *rx = ry - rz; break;
+            case kOpMul: *rx = ry * rz; break;
+            case kOpDiv: *rx = ry / rz; break;
+            case kOpLt: *rx = ry < rz ? 1.0 : 0.0; break;
+            case kOpLe: *rx = ry <= rz ? 1.0 : 0.0; break;
+            case kOpEq: *rx = ry == rz ? 1.0 : 0.0; break;
+            case kOpNe: *rx = ry != rz ? 1.0 : 0.0; break;
+            case kOpNeg: *rx = -ry; break;
+            case kOpNot: *rx = ry == 0.0 ? 1.0 : 0.0; break;
+            case kOpLog: *rx = fn::log(ry); break;
+            case kOpExp: *rx = fn::exp(ry); break;
+            case kOpSqrt: *rx = fn::sqrt(ry); break;
+            case kOpFloor: *rx = __builtin_floor(ry); break;
+            case kOpData: {
+                const uint32_t a0 = P.array_start[imm], a1 = P.array_start[imm + 1];
+                if (!(ry >= 0.0 && ry < (double)(a1 - a0) && ry == __builtin_floor(ry))) fault = true;
+                else *rx = P.data[a0 + (uint32_t)ry];
+                break;
+            }
+            case kOpLen: *rx = (double)(P.array_start[imm + 1] - P.array_start[imm]); break;
+            case kOpSample: {
+                const double v = prog_draw(imm, ry, rz, s, fault);
+                if (!fault) *rx = v;
+                break;
+            }
+            case kOpObserve: {
+                const double d = prog_logpdf(imm, ry, rz, *rx, fault);
+                if (!fault) lw = lw + d;
+                break;
+            }
+            case kOpWeight: lw = lw + *rx; break;
+            case kOpJz:
+                if (*rx == 0.0) pc = imm;
+                break;
+            case kOpJmp: pc = imm; break;
+            case kOpCallFrame:
+                if (imm > P.stack_words - sp) fault = true;
+                break;
+            case kOpStn: st[(uint64_t)(sp + imm) * n + j] = *rx; break;
+            case kOpAddr: *rx = (double)(fp + imm); break;
+            case kOpPush: sp += imm; break;
+            case kOpStret: {
+                const double loc = st[(uint64_t)(fp + 1u) * n + j];
+                if (!(loc >= 0.0 && loc < (double)sp && loc == __builtin_floor(loc))) fault = true;
+                else st[(uint64_t)loc * n + j] = *rx;
+                break;
+            }
+            case kOpGoto:
+            case kOpCkpt:
+            case kOpJret: {
+                uint32_t next = imm;
+                if (op == kOpJret) {
+                    const double ra = st[(uint64_t)fp * n + j];
+                    if (ra == (double)kStop) {
+                        next = kStop;
+                    } else if (ra >= 0.0 && ra < (double)P.n_blocks && ra == __builtin_floor(ra)) {
+                        next = (uint32_t)ra;
+                    } else {
+                        fault = true;
+                        break;
+                    }
+                    sp -= imm;
+                }
+                blk = next;
+                if (next == kStop || op == kOpCkpt) {
+                    live = false;
+                } else {
+                    steps += 1;
+                    pc = P.block_start[next];
+                }
+                break;
+            }
+            default: fault = true; break;  // kOpFault
+            }
+        }
+        if (fault) {
+            lw = -__builtin_huge_val();
+            blk = kStop;
+            sp = 0;
+            live = false;
+        }
+    }
+    if (valid) {
+        out.blk[j] = (uint8_t)blk;
+        out.ints[0][j] = (int32_t)sp;
+        R.lw[j] = lw;
+    }
+    Partial p{0ull, 0u, 0u, 0u};
+    if (valid) {
+        if (lw != lw || lw == __builtin_huge_val()) p.bad = 1;
+        else p.key = order_key(lw);
+        p.act = blk != kStop ? 1u : 0u;
+        p.steps = steps;
+    }
+    publish_tile_partial<kThreads>(R, tile, p, &s_arrived);
+}
+
 // Hidden-lineage stacks live in registers (kRegFrames frames). A particle that
 // needs more is recomputed, in the same work-group, one lane of its wavefront
 // at a time with a kMaxDepthCap-frame stack in LDS; its random stream is
 // counter-based, so the recomputation draws the same words.
 template <int Kind, class Real>
-__device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
+__device__ __forceinline__ void builtin_body(const RunDev& R, uint32_t tile)
 {
     constexpr int kThreads = prop_threads(Kind);
     const uint32_t j = tile * kThreads + threadIdx.x;
@@ -516,6 +702,13 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
         p.steps = steps;
     }
     publish_tile_partial<kThreads>(R, tile, p, &s_arrived);
+}
+
+template <int Kind, class Real>
+__device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
+{
+    if constexpr (Kind == 6) program_body<prop_threads(6)>(R, tile);
+    else builtin_body<Kind, Real>(R, tile);
 }
 
 // Entry points: one run (its record is a kernel argument, tile = work-group)
@@ -1070,6 +1263,7 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     else if (kind == 3) hipLaunchKernelGGL((k_propagate<3, double>), g, b, 0, st, runs, tiles);
     else if (kind == 4 && precision == 32) hipLaunchKernelGGL((k_propagate<4, float>), g, b, 0, st, runs, tiles);
     else if (kind == 4) hipLaunchKernelGGL((k_propagate<4, double>), g, b, 0, st, runs, tiles);
+    else if (kind == 6) hipLaunchKernelGGL((k_propagate<6, double>), g, b, 0, st, runs, tiles);
     else if (precision == 32) hipLaunchKernelGGL((k_propagate<5, float>), g, b, 0, st, runs, tiles);
     else hipLaunchKernelGGL((k_propagate<5, double>), g, b, 0, st, runs, tiles);
     return hipGetLastError();
@@ -1087,6 +1281,7 @@ hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipS
     else if (kind == 3) hipLaunchKernelGGL((k_propagate_one<3, double>), g, b, 0, st, run);
     else if (kind == 4 && precision == 32) hipLaunchKernelGGL((k_propagate_one<4, float>), g, b, 0, st, run);
     else if (kind == 4) hipLaunchKernelGGL((k_propagate_one<4, double>), g, b, 0, st, run);
+    else if (kind == 6) hipLaunchKernelGGL((k_propagate_one<6, double>), g, b, 0, st, run);
     else if (precision == 32) hipLaunchKernelGGL((k_propagate_one<5, float>), g, b, 0, st, run);
     else hipLaunchKernelGGL((k_propagate_one<5, double>), g, b, 0, st, run);
     return hipGetLastError();

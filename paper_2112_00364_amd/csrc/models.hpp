@@ -13,6 +13,17 @@ namespace pcfg {
 
 constexpr uint8_t kStop = 255;  // b_stop
 
+// A compiled program (SMC_MODEL_PROGRAM): bytecode blocks, constants and
+// data arrays; stack_words is each particle's stack capacity.
+struct ProgramDev {
+    const unsigned long long* code;
+    const uint32_t* block_start;
+    const double* consts;
+    const double* data;
+    const uint32_t* array_start;
+    uint32_t n_blocks, n_arrays, stack_words, n_consts;
+};
+
 // Constant model data on the device (uploaded by smc_model_register).
 struct ModelDev {
     int32_t kind, precision, checkpoint, n_nodes, T, stack_depth;
@@ -24,6 +35,7 @@ struct ModelDev {
     double p[16];
     // constants derived on the device with the pinned functions
     double ln2, log_rho, corr, log_w, obs_c, obs_var, ln10;
+    ProgramDev prog;
 };
 
 // ---------------------------------------------------------------------------

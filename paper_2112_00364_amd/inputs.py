@@ -241,3 +241,125 @@ def request_stream(n_requests: int, seed: int, rate_per_s: float,
         out.append({"id": i, "arrival": t, "kind": kind, "tips": n_tips, "n": 1 << k,
                     "tree_seed": tree_seed, "seed": run_seed})
     return out
+
+
+# ---------------------------------------------------------------------------
+# Compiled-program workloads (source text for ppl.compile_program). Numbers are
+# written with repr, so both readers of the text get the same doubles.
+# ---------------------------------------------------------------------------
+def _num(v) -> str:
+    return repr(float(v))
+
+
+def geometric_program(p=0.5, w=1.5) -> str:
+    """Sec. 2 / Fig. 2's weighted geometric program, written recursively with
+    a resample after every heads: the same draws and weights as the built-in
+    geometric model with checkpoints."""
+    return f"""(program
+  (def flip ()
+    (sample h bernoulli {_num(p)})
+    (if h ((weight (log {_num(w)})) (resample) (call r flip) (let n (+ r 1)))
+          ((let n 1)))
+    (return n))
+  (def main () (call n flip) (return n)))"""
+
+
+def lgssm_program(y, a=0.9, b=0.0, q=1.0, r=0.5, m0=0.0, s0=None) -> str:
+    """Eq. (2) / Fig. 4's state-space model as a recursive program: one step
+    per observation, a resample between steps. Written with the built-in
+    LGSSM model's operations (x' = (a x + b) + q z; weight obs_c - d^2 / (2 r^2)),
+    so at FP64 the two give the same bits."""
+    if s0 is None:
+        s0 = math.sqrt(q * q / (1.0 - a * a))
+    ys = " ".join(_num(v) for v in y)
+    return f"""(program
+  (data y {ys})
+  (def step (t x)
+    (sample x1 normal (+ (* {_num(a)} x) {_num(b)}) {_num(q)})
+    (let d (- (at y t) x1))
+    (let c (* -0.5 (log (* 6.283185307179586476925286766559005768394 (* {_num(r)} {_num(r)})))))
+    (weight (- c (/ (* d d) (* 2.0 (* {_num(r)} {_num(r)})))))
+    (if (< (+ t 1) (len y)) ((resample) (call u step (+ t 1) x1)) ())
+    (return 0))
+  (def main ()
+    (sample x0 normal {_num(m0)} {_num(s0)})
+    (call u step 0 x0)
+    (return 0)))"""
+
+
+def hmm_program(ys, p0=0.5, flip=0.2, emit=(0.1, 0.9)) -> str:
+    """Two-state hidden Markov model with binary observations: s_0 ~
+    Bernoulli(p0), the state flips with probability `flip` each step, and
+    y_t ~ Bernoulli(emit[s_t]); a resample between steps."""
+    ys_ = " ".join(_num(v) for v in ys)
+    e0, e1 = emit
+    return f"""(program
+  (data ys {ys_})
+  (def hmm (t s)
+    (sample f bernoulli {_num(flip)})
+    (let s2 (+ s (* f (- 1 (* 2 s)))))
+    (observe bernoulli (+ {_num(e0)} (* {_num(e1 - e0)} s2)) (at ys t))
+    (if (< (+ t 1) (len ys)) ((resample) (call u hmm (+ t 1) s2)) ())
+    (return 0))
+  (def main ()
+    (sample s0 bernoulli {_num(p0)})
+    (call u hmm 0 s0)
+    (return 0)))"""
+
+
+def branching_program(obs) -> str:
+    """A program with stochastic branching, a recursion that checkpoints at
+    every level, a resample-free recursion, an inlined helper and every
+    sampler: the recursive `walk` moves x by one of two kernels, then simulates
+    a random-depth sum by recursion and observes obs[t]."""
+    os_ = " ".join(_num(v) for v in obs)
+    return f"""(program
+  (data obs {os_})
+  (def sq (v) (return (* v v)))
+  (def depth_sum (d)
+    (if (<= d 0) ((let s 0))
+                 ((sample u uniform 0 1) (call r depth_sum (- d 1)) (let s (+ r u))))
+    (return s))
+  (def walk (t x)
+    (sample b bernoulli 0.3)
+    (if b ((sample x2 normal x 2.0))
+          ((sample g gamma 2.0 0.5) (let x2 (- (* 0.9 x) (* 0.1 g)))))
+    (sample k poisson 1.5)
+    (call extra depth_sum k)
+    (call e sq (- x2 (at obs t)))
+    (weight (* -0.05 e))
+    (observe normal (at obs t) (+ x2 (* 0.1 extra)) 1.5)
+    (sample c binomial 10 0.3)
+    (observe poisson 2.0 c)
+    (sample bb beta 2.0 3.0)
+    (sample ee exponential 2.0)
+    (observe exponential 2.0 ee)
+    (observe uniform 0 1 bb)
+    (if (< (+ t 1) (len obs)) ((resample) (call r walk (+ t 1) x2)) ((let r x2)))
+    (return r))
+  (def main ()
+    (sample x0 normal 0 1)
+    (call r walk 0 x0)
+    (return r)))"""
+
+
+def hmm_observations(T: int, seed: int, p0=0.5, flip=0.2, emit=(0.1, 0.9)) -> list:
+    """Binary observations simulated from hmm_program's model."""
+    rng = np.random.default_rng(seed)
+    s = int(rng.random() < p0)
+    ys = []
+    for _ in range(T):
+        if rng.random() < flip:
+            s = 1 - s
+        ys.append(float(rng.random() < emit[s]))
+    return ys
+
+
+def branching_observations(T: int, seed: int) -> list:
+    """Observations for branching_program: a slow random walk, rounded to 1/8."""
+    rng = np.random.default_rng(seed)
+    x, out = 0.0, []
+    for _ in range(T):
+        x = 0.9 * x + rng.normal(0.0, 0.7)
+        out.append(round(x * 8.0) / 8.0)
+    return out

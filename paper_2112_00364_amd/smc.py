@@ -20,7 +20,7 @@ OK, FINISHED = 0, 1
 ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_STATE, ERR_NAN, DEGENERATE = -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "OK", 1: "FINISHED", -1: "ERR_INVALID", -2: "ERR_OOM", -3: "ERR_DEVICE",
                 -4: "ERR_STATE", -5: "ERR_NAN", -6: "DEGENERATE"}
-KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3, "seir": 4, "crbd_ds": 5}
+KINDS = {"geometric": 0, "lgssm": 1, "crbd": 2, "clads": 3, "seir": 4, "crbd_ds": 5, "program": 6}
 READ_BLK, READ_LW, READ_ANC, READ_FIELD0 = 0, 1, 2, 16
 STOP = 255
 
@@ -33,6 +33,8 @@ FIELDS = {
     "crbd_ds": (4, ["a_lambda", "th_lambda", "a_mu", "th_mu", "node"]),
     "seir": (6, ["hLambda", "hDelta", "hGamma", "mLambda", "mDelta", "rho",
                  "hS", "hE", "hI", "hR", "mS", "mE", "mI", "mR", "z", "t"]),
+    # compiled programs: the stack pointer, then the stack ([particle][word], FP64)
+    "program": (0, ["sp", "stack"]),
 }
 
 
@@ -42,13 +44,55 @@ class SMCError(RuntimeError):
         self.code = code
 
 
+class _ProgramDesc(C.Structure):
+    _fields_ = [
+        ("n_blocks", C.c_uint32), ("block_start", C.POINTER(C.c_uint32)), ("code", C.POINTER(C.c_uint64)),
+        ("n_code", C.c_uint32), ("consts", C.POINTER(C.c_double)), ("n_consts", C.c_uint32),
+        ("data", C.POINTER(C.c_double)), ("n_data", C.c_uint32), ("array_start", C.POINTER(C.c_uint32)),
+        ("n_arrays", C.c_uint32), ("stack_words", C.c_uint32),
+    ]
+
+
 class _Desc(C.Structure):
     _fields_ = [
         ("kind", C.c_int32), ("precision", C.c_int32), ("checkpoint", C.c_int32), ("n_nodes", C.c_int32),
         ("parent", C.POINTER(C.c_int32)), ("left", C.POINTER(C.c_int32)), ("right", C.POINTER(C.c_int32)),
         ("age", C.POINTER(C.c_double)), ("T", C.c_int32), ("y", C.POINTER(C.c_double)),
-        ("params", C.c_double * 16), ("ess_threshold", C.c_double),
+        ("params", C.c_double * 16), ("ess_threshold", C.c_double), ("program", C.POINTER(_ProgramDesc)),
     ]
+
+
+def program_desc(img, keep: list) -> _ProgramDesc:
+    """C description of a compiled program image (ppl.ProgramImage or a dict of
+    its arrays); the arrays it points to are appended to keep."""
+    get = (lambda name: img[name]) if isinstance(img, dict) else (lambda name: getattr(img, name))
+    code = np.ascontiguousarray(get("code"), dtype=np.uint64)
+    starts = np.ascontiguousarray(get("block_start"), dtype=np.uint32)
+    consts = np.ascontiguousarray(get("consts"), dtype=np.float64)
+    data = np.ascontiguousarray(get("data"), dtype=np.float64)
+    astart = np.ascontiguousarray(get("array_start"), dtype=np.uint32)
+    keep += [code, starts, consts, data, astart]
+    d = _ProgramDesc()
+    d.n_blocks = max(len(starts) - 1, 0)
+    d.block_start = starts.ctypes.data_as(C.POINTER(C.c_uint32))
+    d.code = code.ctypes.data_as(C.POINTER(C.c_uint64))
+    d.n_code = len(code)
+    d.consts = consts.ctypes.data_as(C.POINTER(C.c_double))
+    d.n_consts = len(consts)
+    d.data = data.ctypes.data_as(C.POINTER(C.c_double))
+    d.n_data = len(data)
+    d.array_start = astart.ctypes.data_as(C.POINTER(C.c_uint32))
+    d.n_arrays = max(len(astart) - 1, 0)
+    d.stack_words = int(get("stack_words"))
+    return d
+
+
+def check_program(img):
+    """Validate a program image with the library's checks (no device needed):
+    raises SMCError(ERR_INVALID) naming the first problem."""
+    keep = []
+    d = program_desc(img, keep)
+    _check(lib().smc_program_check(C.byref(d)))
 
 
 class _Stats(C.Structure):
@@ -84,6 +128,7 @@ def lib():
         "smc_ctx_create": [i32, vp, vp, C.POINTER(vp)],
         "smc_ctx_destroy": [vp],
         "smc_model_register": [vp, C.POINTER(_Desc), C.POINTER(vp)],
+        "smc_program_check": [C.POINTER(_ProgramDesc)],
         "smc_model_destroy": [vp],
         "smc_init": [vp, u64, u64, C.POINTER(vp)],
         "smc_step": [vp], "smc_resample": [vp],
@@ -221,6 +266,9 @@ class Model:
         for i, v in enumerate(spec.get("params", [])):
             d.params[i] = float(v)
         d.ess_threshold = float(spec.get("ess_threshold", 0.0))
+        if spec["kind"] == "program":
+            self._program = program_desc(spec["program"], self._keep)
+            d.program = C.pointer(self._program)
         h = C.c_void_p()
         _check(L.smc_model_register(ctx._h, C.byref(d), C.byref(h)))
         self._h = h

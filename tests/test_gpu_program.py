@@ -1,0 +1,234 @@
+"""Compiled programs on the GPU (SMC_MODEL_PROGRAM) against the source-level
+oracle, through the C interface.
+
+Bar: log-weights, ancestors and the stopped set bit-exact every round; log Z
+within 1e-9 relative (in practice equal); stack pointers and live stack words
+equal to those of a sequential simulation of the same bytecode. The
+geometric and state-space programs must also reproduce the library's
+built-in models bit for bit.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2112_00364_amd import inputs as I
+from paper_2112_00364_amd import ppl
+
+pytestmark = pytest.mark.gpu
+
+LOGZ_RTOL = 1e-9
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def smc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_00364_amd import smc as S
+    S.lib()
+    return S
+
+
+@pytest.fixture(scope="module")
+def ctx(smc):
+    c = smc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def PO(oracle):
+    from oracle import ppl_oracle
+    return ppl_oracle
+
+
+PROGRAMS = {
+    "geometric": lambda: I.geometric_program(0.5, 1.2),
+    "lgssm": lambda: I.lgssm_program(I.lgssm_data(16, 2000)),
+    "hmm": lambda: I.hmm_program(I.hmm_observations(14, 7)),
+    "branching": lambda: I.branching_program(I.branching_observations(7, 8)),
+}
+
+
+def program_model(smc, ctx, txt, stack_words=256, ess=0.0):
+    img = ppl.compile_program(txt, stack_words)
+    return smc.Model(ctx, {"kind": "program", "precision": 64, "program": img, "ess_threshold": ess}), img
+
+
+def bits(a):
+    return np.asarray(a, dtype=np.float64).view(np.uint64)
+
+
+def lockstep(smc, run, ref, oracle, label):
+    rounds = 0
+    while True:
+        say(label, "round", rounds)
+        run.step()
+        ref.step()
+        lw = run.lw()
+        assert np.array_equal(bits(lw), bits(ref.lw)), (label, rounds, np.flatnonzero(bits(lw) != bits(ref.lw))[:5])
+        assert np.array_equal(run.blk() == 255, ref.stopped()), (label, rounds)
+        sg = run.resample()
+        sr = ref.resample()
+        done, st = run.done()
+        assert st == sr, (label, rounds, st, sr)
+        if sr != oracle.OK:
+            break
+        assert np.array_equal(run.anc(), ref.anc), (label, rounds)
+        rounds += 1
+    lz = run.log_z()
+    if math.isfinite(ref.log_z):
+        assert abs(lz - ref.log_z) <= LOGZ_RTOL * max(1.0, abs(ref.log_z)), (label, lz, ref.log_z)
+    else:
+        assert lz == ref.log_z
+    return rounds
+
+
+@pytest.mark.parametrize("name", list(PROGRAMS))
+@pytest.mark.parametrize("n", [1, 1000, 4099])
+def test_program_matches_oracle(smc, ctx, oracle, PO, name, n):
+    if name in ("lgssm", "branching") and n == 4099:
+        n = 2051  # the pure-Python oracle sets the size
+    txt = PROGRAMS[name]()
+    model, _ = program_model(smc, ctx, txt)
+    for seed in (3, 4):
+        run = smc.Run(model, n, seed)
+        ref = PO.ProgramRun(txt, n, seed)
+        lockstep(smc, run, ref, oracle, f"{name} n={n} seed={seed}")
+        run.close()
+    model.close()
+
+
+@pytest.mark.parametrize("n", [1 << 16, 100003])
+def test_geometric_program_equals_builtin(smc, ctx, n):
+    model, _ = program_model(smc, ctx, I.geometric_program(0.5, 1.2))
+    builtin = smc.Model(ctx, I.geometric_spec(True, 0.5, 1.2))
+    for seed in (1, 2):
+        say("geometric program vs built-in", n, seed)
+        a = smc.Run(model, n, seed)
+        b = smc.Run(builtin, n, seed)
+        assert a.run_to_end() == b.run_to_end() == smc.FINISHED
+        assert a.log_z() == b.log_z()
+        assert a.stats()["round"] == b.stats()["round"]
+        a.close()
+        b.close()
+
+
+def test_lgssm_program_equals_builtin(smc, ctx):
+    y = I.lgssm_data(100, 2000)
+    model, _ = program_model(smc, ctx, I.lgssm_program(y))
+    builtin = smc.Model(ctx, I.lgssm_spec(y, 64))
+    n = 1 << 16
+    a = smc.Run(model, n, 9)
+    b = smc.Run(builtin, n, 9)
+    for r in range(100):
+        a.step()
+        b.step()
+        if r % 33 == 0:
+            say("lgssm program vs built-in round", r)
+            assert np.array_equal(bits(a.lw()), bits(b.lw()))
+        sa, sb = a.resample(), b.resample()
+        assert sa == sb
+        if sa != smc.OK:
+            break
+    assert a.log_z() == b.log_z()
+
+
+def test_stack_contents_match_bytecode_simulation(smc, ctx, oracle):
+    import bytecode_sim as BS
+    txt = PROGRAMS["branching"]()
+    model, img = program_model(smc, ctx, txt, stack_words=64)
+    n = 300
+    run = smc.Run(model, n, 21)
+    sim = BS.SimRun(img, n, 21)
+    while sim.status == oracle.OK:
+        say("stack round", sim.round)
+        run.step()
+        sim.step()
+        sp = run.field(0, np.int32)
+        assert np.array_equal(sp, np.array([q[1] for q in sim.p], dtype=np.int32))
+        stack = run.field(1, np.float64, count=img.stack_words)
+        for j in range(n):
+            k = int(sp[j])
+            assert np.array_equal(bits(stack[j, :k]), bits(np.array(sim.p[j][2][:k], dtype=np.float64))), (j, k)
+        run.resample()
+        sim.resample()
+    assert run.log_z() == sim.log_z
+
+
+def test_stack_overflow_faults_particles(smc, ctx, oracle):
+    """A stack of 12 words holds main's frame (3) and one flip frame (5) but
+    not a second flip frame: particles with two heads fault (weight -inf,
+    stopped) without touching memory beyond their stack."""
+    import bytecode_sim as BS
+    txt = I.geometric_program(0.5, 1.2)
+    model, img = program_model(smc, ctx, txt, stack_words=12)
+    n = 4096
+    run = smc.Run(model, n, 5)
+    sim = BS.SimRun(img, n, 5)
+    while sim.status == oracle.OK:
+        run.step()
+        sim.step()
+        assert np.array_equal(bits(run.lw()), bits(sim.lw()))
+        run.resample()
+        sim.resample()
+        assert run.done()[1] == sim.status
+    assert run.log_z() == sim.log_z
+
+
+def test_program_with_ess_rule(smc, ctx, oracle, PO):
+    txt = I.lgssm_program(I.lgssm_data(20, 2000))
+    model, _ = program_model(smc, ctx, txt, ess=0.5)
+    run = smc.Run(model, 777, 6)
+    ref = PO.ProgramRun(txt, 777, 6, ess_threshold=0.5)
+    lockstep(smc, run, ref, oracle, "lgssm ess")
+    assert run.stats()["resamples"] == ref.resamples and 0 < ref.resamples < ref.round
+
+
+def test_run_to_end_and_reset(smc, ctx):
+    txt = PROGRAMS["branching"]()
+    model, _ = program_model(smc, ctx, txt)
+    n = 1 << 14
+    a = smc.Run(model, n, 2)
+    stepwise = a
+    while True:
+        stepwise.step()
+        if stepwise.resample() != smc.OK:
+            break
+    lz = stepwise.log_z()
+    b = smc.Run(model, n, 2)
+    assert b.run_to_end() == smc.FINISHED
+    assert b.log_z() == lz
+    b.reset(2)
+    assert b.run_to_end() == smc.FINISHED
+    assert b.log_z() == lz
+
+
+def test_programs_in_a_batch(smc, ctx):
+    progs = [PROGRAMS[k]() for k in ("hmm", "branching", "geometric")]
+    models = [program_model(smc, ctx, t)[0] for t in progs] + [smc.Model(ctx, I.geometric_spec(True, 0.5, 1.2))]
+    sizes = [700, 2500, 5000, 3000]
+    alone = []
+    for m, nn in zip(models, sizes):
+        r = smc.Run(m, nn, 8)
+        r.run_to_end()
+        alone.append(r.log_z())
+        r.close()
+    b = smc.Batch(ctx)
+    slots = [b.add(m, nn, 8) for m, nn in zip(models, sizes)]
+    for _ in range(200):
+        b.tick(4)
+        done, lz, st, _ = b.poll()
+        if done.all():
+            break
+    assert done.all()
+    for s, want in zip(slots, alone):
+        assert lz[s] == want
+    b.close()

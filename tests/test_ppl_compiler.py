@@ -1,0 +1,383 @@
+"""The program compiler (Sec. 4) on the CPU: Algorithm 2, code generation and
+the library's validation of program images.
+
+What pins it, from outside the compiler:
+* Algorithm 2 on Fig. 6(a) gives Fig. 6(b) (golden fixture from the paper);
+* on random statement trees, executing the decomposed blocks emits the same
+  sequence of statements, checkpoints and calls as executing the source, and
+  checkpoints and calls only end blocks (the property Sec. 4.2 states);
+* compiled programs run by a sequential bytecode simulator give, round by
+  round, the same log-weights and ancestors as the source-level oracle.
+"""
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+from paper_2112_00364_amd import inputs as I
+from paper_2112_00364_amd import ppl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# --- Algorithm 2 -----------------------------------------------------------------
+
+def _abstract(x):
+    """Fixture form (lists) -> the decomposer's abstract input (tuples for ifs)."""
+    if isinstance(x, list):
+        assert x[0] == "if"
+        return ("if", [_abstract(s) for s in x[1]], [_abstract(s) for s in x[2]])
+    return x
+
+
+def _canon(block, rename):
+    """Decomposer output -> fixture form with renamed block numbers."""
+    out = []
+    for it in block:
+        k = it[0]
+        if k == "other":
+            out.append("other")
+        elif k in ("checkpoint", "call", "jump"):
+            out.append([k, it[1] if it[1] == ppl.RETURN else rename[it[1]]])
+        else:
+            out.append(["if", _canon(it[2], rename), _canon(it[3], rename)])
+    return out
+
+
+def _targets(block):
+    for it in block:
+        if it[0] in ("checkpoint", "call", "jump"):
+            yield it[1]
+        elif it[0] == "if":
+            yield from _targets(it[2])
+            yield from _targets(it[3])
+
+
+def _iso(entry, blocks, fig_entry, fig_blocks):
+    """Is (entry, blocks) the figure's result up to a renaming of block numbers?"""
+    rename = {entry: fig_entry}
+    todo = [entry]
+    while todo:
+        b = todo.pop()
+        for t in _targets(blocks[b]):
+            if t != ppl.RETURN and t not in rename:
+                rename[t] = None
+                todo.append(t)
+    # fix the renaming by walking both structures in order
+    def walk(mine, fig):
+        if len(mine) != len(fig):
+            return False
+        for m, f in zip(mine, fig):
+            if m[0] == "other":
+                if f != "other":
+                    return False
+            elif m[0] in ("checkpoint", "call", "jump"):
+                if not isinstance(f, list) or f[0] != m[0]:
+                    return False
+                if m[1] == ppl.RETURN or f[1] == "return":
+                    if not (m[1] == ppl.RETURN and f[1] == "return"):
+                        return False
+                elif rename.get(m[1]) is None:
+                    rename[m[1]] = f[1]
+                elif rename[m[1]] != f[1]:
+                    return False
+            else:
+                if not isinstance(f, list) or f[0] != "if":
+                    return False
+                if not (walk(m[2], f[1]) and walk(m[3], f[2])):
+                    return False
+        return True
+
+    seen = set()
+    todo = [entry]
+    while todo:
+        b = todo.pop()
+        if b in seen:
+            continue
+        seen.add(b)
+        if not walk(blocks[b], fig_blocks[rename[b]]):
+            return False
+        todo += [t for t in _targets(blocks[b]) if t != ppl.RETURN]
+    return len(seen) == len(blocks) == len(fig_blocks) and len(set(rename.values())) == len(rename)
+
+
+def test_algorithm2_reproduces_fig6():
+    fx = json.load(open(os.path.join(HERE, "golden", "alg2_fig6.json")))
+    entry, blocks = ppl.decompose_abstract([_abstract(s) for s in fx["input"]])
+    fig_blocks = {int(k): [_fix(s) for s in v] for k, v in fx["blocks"].items()}
+    assert _iso(entry, blocks, fx["entry"], fig_blocks), (entry, blocks)
+
+
+def _fix(s):
+    if isinstance(s, list) and s[0] == "if":
+        return ["if", [_fix(t) for t in s[1]], [_fix(t) for t in s[2]]]
+    return s
+
+
+def test_algorithm2_catches_a_wrong_figure():
+    """The isomorphism check is not vacuous: a changed jump target fails it."""
+    fx = json.load(open(os.path.join(HERE, "golden", "alg2_fig6.json")))
+    entry, blocks = ppl.decompose_abstract([_abstract(s) for s in fx["input"]])
+    fig_blocks = {int(k): [_fix(s) for s in v] for k, v in fx["blocks"].items()}
+    fig_blocks[3] = ["other", ["jump", "return"]]
+    assert not _iso(entry, blocks, fx["entry"], fig_blocks)
+
+
+def _random_program(rng, depth=0, label=None):
+    label = label if label is not None else [0]
+    out = []
+    for _ in range(rng.randint(0, 5)):
+        r = rng.random()
+        if r < 0.45 or depth >= 3:
+            label[0] += 1
+            out.append(("other", label[0]))
+        elif r < 0.6:
+            label[0] += 1
+            out.append(("checkpoint", label[0]))
+        elif r < 0.75:
+            label[0] += 1
+            out.append(("call", label[0]))
+        else:
+            out.append(("if", _random_program(rng, depth + 1, label), _random_program(rng, depth + 1, label)))
+    return out
+
+
+def _run_source(stmts, decide, events):
+    for s in stmts:
+        if s[0] == "if":
+            _run_source(s[1] if decide() else s[2], decide, events)
+        else:
+            events.append(s)
+
+
+def _run_blocks(entry, blocks, decide, events):
+    """Executes decomposed blocks; checkpoints and calls are events that then
+    continue at their block (calls return immediately in this abstraction)."""
+    b = entry
+    for _ in range(10000):
+        nxt = _exec(blocks[b], decide, events)
+        if nxt == ppl.RETURN:
+            return
+        assert nxt is not None, "block fell through"
+        b = nxt
+    raise AssertionError("no termination")
+
+
+def _exec(block, decide, events):
+    for i, it in enumerate(block):
+        k = it[0]
+        if k == "other":
+            events.append(it[1])
+        elif k in ("checkpoint", "call"):
+            assert i == len(block) - 1, "checkpoint or call not at the end of its block"
+            events.append(it[2])
+            return it[1]
+        elif k == "jump":
+            assert i == len(block) - 1
+            return it[1]
+        else:
+            r = _exec(it[2] if decide() else it[3], decide, events)
+            if r is not None:  # a branch left the block: the if must be its last statement
+                assert i == len(block) - 1
+                return r
+    return None
+
+
+@pytest.mark.parametrize("seed", range(200))
+def test_algorithm2_preserves_execution_order(seed):
+    rng = random.Random(seed)
+    prog = _random_program(rng)
+
+    def kind(s):
+        return s[0] if s[0] != "if" else "if"
+
+    import itertools
+    d = ppl.Decomposer(kind, itertools.count(1))
+    d.branches = lambda s: (s[1], s[2])
+    entry, blocks = d.decompose(prog)
+    for trial in range(20):
+        choices = [rng.random() < 0.5 for _ in range(200)]
+        it1, it2 = iter(choices), iter(choices)
+        ev_src, ev_blk = [], []
+        _run_source(prog, lambda: next(it1), ev_src)
+        _run_blocks(entry, blocks, lambda: next(it2), ev_blk)
+        assert ev_src == ev_blk, (prog, blocks)
+
+
+# --- compiler front end ------------------------------------------------------------
+
+@pytest.mark.parametrize("text,msg", [
+    ("(program (def main () (return x)))", "read before"),
+    ("(program (def main () (if 1 ((let a 1)) ()) (return a)))", "read before"),
+    ("(program (def main () (return 1) (let a 2)))", "last statement"),
+    ("(program (def main () (call a nope)))", "unknown function"),
+    ("(program (def f (p) (return p)) (def main () (call a f 1 2)))", "wrong number"),
+    ("(program (def main (x) (return x)))", "main"),
+    ("(program (def main () (sample a normal 0)))", "bad sample"),
+    ("(program (def main () (observe gamma 1 1 1)))", "bad observe"),
+    ("(program (def f () (if 1 ((return 1)) ((return 2)))) (def main () (call a f)))", "inside an if"),
+    ("(program (def main () (let a (at nothere 0))))", "unknown data"),
+    ("(program (def main () (let a (+ 1 2 3))))", "two operands"),
+])
+def test_compiler_rejects(text, msg):
+    with pytest.raises(ppl.CompileError, match=msg):
+        ppl.compile_program(text)
+
+
+def test_frames_and_inlining():
+    img = ppl.compile_program(I.branching_program([0.1, 0.2]))
+    # sq is resample-free and not recursive: inlined, no frame of its own
+    assert "sq" not in img.frames
+    # depth_sum is resample-free but recursive: it keeps a frame on the stack
+    assert img.frames["depth_sum"] == 2 + 4  # ra, return slot, d, s, u, r
+    assert img.entry["main"] == 1 and img.block_names[0] == "start"
+
+
+def test_program_too_deep_for_registers():
+    e = "1"
+    for _ in range(20):
+        e = f"(+ 1 {e})"
+    with pytest.raises(ppl.CompileError, match="registers"):
+        ppl.compile_program(f"(program (def main () (let a (+ {e} {e}))))")
+
+
+# --- the library's program validation (no device needed) ----------------------------
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2112_00364_amd import smc
+    smc.lib()
+    return smc
+
+
+def _img_dict(img):
+    return {k: np.array(getattr(img, k)).copy() for k in ("code", "block_start", "consts", "data", "array_start")} | \
+        {"stack_words": img.stack_words}
+
+
+def _enc(op, x=0, y=0, z=0, imm=0):
+    return ppl.OPS[op] | (x << 8) | (y << 16) | (z << 24) | ((imm & 0xFFFFFFFF) << 32)
+
+
+@pytest.mark.parametrize("name", ["geometric", "lgssm", "hmm", "branching"])
+def test_compiled_programs_pass_validation(S, name):
+    txt = {"geometric": I.geometric_program(0.5, 1.2), "lgssm": I.lgssm_program(I.lgssm_data(5, 1)),
+           "hmm": I.hmm_program([1, 0, 1]), "branching": I.branching_program([0.3, 0.2])}[name]
+    S.check_program(ppl.compile_program(txt))
+
+
+def _mutations(img):
+    """(description, mutated image) pairs that the validator must reject."""
+    base = _img_dict(img)
+    code = base["code"]
+    starts = base["block_start"]
+    # find instructions by opcode
+    def where(op):
+        return [i for i, w in enumerate(code) if int(w) & 255 == ppl.OPS[op]]
+
+    def with_code(i, word):
+        d = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in base.items()}
+        d["code"][i] = np.uint64(word)
+        return d
+
+    out = []
+    i = where("LDF")[0]
+    out.append(("opcode", with_code(i, _enc("FAULT") + 200 - ppl.OPS["FAULT"])))
+    out.append(("register", with_code(i, _enc("LDF", x=16, imm=2))))
+    out.append(("frame offset", with_code(i, _enc("LDF", imm=200))))
+    c = where("CONST")[0]
+    out.append(("constant", with_code(c, _enc("CONST", imm=10 ** 6))))
+    g = where("GOTO")[0]
+    out.append(("block", with_code(g, _enc("GOTO", imm=300))))
+    out.append(("terminator", with_code(int(starts[1]) - 1, _enc("MOV"))))
+    out.append(("FRAME", with_code(int(starts[1]), _enc("MOV"))))
+    out.append(("FRAME", with_code(int(starts[1]) + 1, _enc("FRAME", imm=3))))
+    j = where("JZ")[0] if where("JZ") else None
+    if j is not None:
+        out.append(("jump", with_code(j, _enc("JZ", imm=j))))
+        out.append(("jump", with_code(j, _enc("JZ", imm=j + 10 ** 5))))
+    s = where("STN")[0]
+    out.append(("STN", with_code(s, _enc("STN", imm=99))))
+    p = where("PUSH")[0]
+    out.append(("PUSH", with_code(p, _enc("PUSH", imm=1))))
+    cf = where("CALLFRAME")[0]
+    out.append(("callee frame", with_code(cf, _enc("CALLFRAME", imm=0))))
+    out.append(("callee frame", with_code(cf, _enc("CALLFRAME", imm=10 ** 6))))
+    ob = where("OBSERVE")
+    if ob:
+        out.append(("observed", with_code(ob[0], _enc("OBSERVE", x=2, y=0, z=1, imm=3))))
+    sm = where("SAMPLE")[0]
+    out.append(("distribution", with_code(sm, _enc("SAMPLE", imm=9))))
+    r = where("JRET")[0]
+    out.append(("JRET", with_code(r, _enc("JRET", imm=1))))
+    d = dict(base)
+    d["stack_words"] = 0
+    out.append(("stack_words", d))
+    d = dict(base)
+    d["stack_words"] = 5000
+    out.append(("stack_words", d))
+    d = dict(base)
+    d["block_start"] = base["block_start"].copy()
+    d["block_start"][-1] += 1
+    out.append(("block_start", d))
+    d = dict(base)
+    d["block_start"] = base["block_start"][:1]
+    out.append(("n_blocks", d))
+    return out
+
+
+def test_validation_rejects_each_rule(S):
+    img = ppl.compile_program(I.branching_program([0.3, 0.2]))
+    for what, bad in _mutations(img):
+        with pytest.raises(S.SMCError) as e:
+            S.check_program(bad)
+        assert e.value.code == S.ERR_INVALID, what
+
+
+def test_validation_rejects_jump_into_open_frame(S):
+    """A jump that skips CALLFRAME but lands on its STN would bypass the
+    capacity check: rejected."""
+    code = [_enc("FRAME", imm=2), _enc("IMM", imm=0), _enc("JZ", imm=4), _enc("CALLFRAME", imm=3),
+            _enc("STN", imm=2), _enc("PUSH", imm=3), _enc("FAULT")]
+    img = {"code": np.array(code, dtype=np.uint64), "block_start": np.array([0, len(code)], dtype=np.uint32),
+           "consts": np.zeros(1), "data": np.zeros(1), "array_start": np.zeros(1, dtype=np.uint32),
+           "stack_words": 8}
+    with pytest.raises(S.SMCError, match="jump"):
+        S.check_program(img)
+    code[2] = _enc("JZ", imm=6)  # jumping over the whole call sequence is fine
+    img["code"] = np.array(code, dtype=np.uint64)
+    S.check_program(img)
+
+
+# --- compiled bytecode against the source-level oracle ------------------------------
+
+PROGRAMS = {
+    "geometric": (lambda: I.geometric_program(0.5, 1.2), 64),
+    "lgssm": (lambda: I.lgssm_program(I.lgssm_data(12, 2000)), 96),
+    "hmm": (lambda: I.hmm_program(I.hmm_observations(10, 7)), 64),
+    "branching": (lambda: I.branching_program(I.branching_observations(6, 8)), 96),
+}
+
+
+@pytest.mark.parametrize("name", PROGRAMS)
+def test_bytecode_matches_source_oracle(oracle, name):
+    import bytecode_sim as BS
+    from oracle import ppl_oracle as PO
+    make, n = PROGRAMS[name]
+    txt = make()
+    img = ppl.compile_program(txt, 256)
+    for seed in (0, 1):
+        a = PO.ProgramRun(txt, n, seed)
+        b = BS.SimRun(img, n, seed)
+        while a.status == oracle.OK:
+            a.step()
+            b.step()
+            assert np.array_equal(a.lw.view(np.uint64), b.lw().view(np.uint64)), (name, seed, a.round)
+            assert np.array_equal(a.stopped(), np.array([q[0] == 255 for q in b.p]))
+            a.resample()
+            b.resample()
+            assert a.status == b.status
+            assert np.array_equal(a.anc, b.anc)
+        assert a.log_z == b.log_z
