@@ -279,7 +279,8 @@ class Model:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().smc_model_destroy(self._h)
+            if self.ctx._h is not None:  # after the context is gone its memory is gone too
+                lib().smc_model_destroy(self._h)
             self._h = None
 
 
@@ -351,7 +352,8 @@ class Run:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().smc_run_destroy(self._h)
+            if self.model.ctx._h is not None:  # a run outliving its context is only forgotten
+                lib().smc_run_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -395,5 +397,6 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().smc_batch_destroy(self._h)
+            if self.ctx._h is not None:
+                lib().smc_batch_destroy(self._h)
             self._h = None

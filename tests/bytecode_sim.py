@@ -67,6 +67,7 @@ def run_blocks(img, code, p, seed, slot, rnd):
                 elif op == "MOV":
                     reg[x] = reg[y]
                 elif op == "LDF":
+                    assert st[fp + imm] is not None, "read of an unwritten stack word"
                     reg[x] = st[fp + imm]
                 elif op == "STF":
                     st[fp + imm] = reg[x]
@@ -165,7 +166,8 @@ class SimRun:
         self.img, self.n, self.seed = img, int(n), int(seed)
         self.code = [decode(w) for w in img.code]
         self.ess = float(ess_threshold)
-        self.p = [[0, 0, [0.0] * img.stack_words, 0.0] for _ in range(self.n)]
+        # None marks a stack word no instruction has written (its device value is undefined)
+        self.p = [[0, 0, [None] * img.stack_words, 0.0] for _ in range(self.n)]
         self.round, self.log_z, self.status, self.block_steps = 0, 0.0, O.OK, 0
         self.anc = np.arange(self.n, dtype=np.uint32)
 
@@ -201,7 +203,7 @@ class SimRun:
         self.log_z += inc
         self.anc = anc
         # live-prefix copy: words beyond sp are not carried
-        self.p = [[self.p[a][0], self.p[a][1], self.p[a][2][:self.p[a][1]] + [0.0] * (self.img.stack_words - self.p[a][1]),
+        self.p = [[self.p[a][0], self.p[a][1], self.p[a][2][:self.p[a][1]] + [None] * (self.img.stack_words - self.p[a][1]),
                    0.0] for a in anc]
         self.round += 1
         return O.OK

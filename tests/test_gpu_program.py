@@ -66,6 +66,10 @@ def bits(a):
     return np.asarray(a, dtype=np.float64).view(np.uint64)
 
 
+def same_log_z(a, b):
+    return a == b or abs(a - b) <= LOGZ_RTOL * max(1.0, abs(b))
+
+
 def lockstep(smc, run, ref, oracle, label):
     rounds = 0
     while True:
@@ -123,7 +127,8 @@ def test_geometric_program_equals_builtin(smc, ctx, n):
 
 def test_lgssm_program_equals_builtin(smc, ctx):
     y = I.lgssm_data(100, 2000)
-    model, _ = program_model(smc, ctx, I.lgssm_program(y))
+    # one 8-word frame per observation on top of main's 3 words
+    model, _ = program_model(smc, ctx, I.lgssm_program(y), stack_words=1024)
     builtin = smc.Model(ctx, I.lgssm_spec(y, 64))
     n = 1 << 16
     a = smc.Run(model, n, 9)
@@ -144,7 +149,7 @@ def test_lgssm_program_equals_builtin(smc, ctx):
 def test_stack_contents_match_bytecode_simulation(smc, ctx, oracle):
     import bytecode_sim as BS
     txt = PROGRAMS["branching"]()
-    model, img = program_model(smc, ctx, txt, stack_words=64)
+    model, img = program_model(smc, ctx, txt, stack_words=256)
     n = 300
     run = smc.Run(model, n, 21)
     sim = BS.SimRun(img, n, 21)
@@ -157,10 +162,14 @@ def test_stack_contents_match_bytecode_simulation(smc, ctx, oracle):
         stack = run.field(1, np.float64, count=img.stack_words)
         for j in range(n):
             k = int(sp[j])
-            assert np.array_equal(bits(stack[j, :k]), bits(np.array(sim.p[j][2][:k], dtype=np.float64))), (j, k)
+            want = sim.p[j][2][:k]
+            written = np.array([v is not None for v in want], dtype=bool)
+            ref = np.array([0.0 if v is None else v for v in want], dtype=np.float64)
+            assert np.array_equal(bits(stack[j, :k])[written], bits(ref)[written]), (j, k)
         run.resample()
         sim.resample()
-    assert run.log_z() == sim.log_z
+    # parallel vs serial summation of exp(lw - M): equal within the log Z bar
+    assert math.isfinite(sim.log_z) and same_log_z(run.log_z(), sim.log_z)
 
 
 def test_stack_overflow_faults_particles(smc, ctx, oracle):
@@ -180,7 +189,7 @@ def test_stack_overflow_faults_particles(smc, ctx, oracle):
         run.resample()
         sim.resample()
         assert run.done()[1] == sim.status
-    assert run.log_z() == sim.log_z
+    assert same_log_z(run.log_z(), sim.log_z)
 
 
 def test_program_with_ess_rule(smc, ctx, oracle, PO):
@@ -197,12 +206,13 @@ def test_run_to_end_and_reset(smc, ctx):
     model, _ = program_model(smc, ctx, txt)
     n = 1 << 14
     a = smc.Run(model, n, 2)
-    stepwise = a
-    while True:
-        stepwise.step()
-        if stepwise.resample() != smc.OK:
+    for _ in range(100):  # smc_resample only enqueues: the status comes from done()
+        a.step()
+        a.resample()
+        if a.done()[0]:
             break
-    lz = stepwise.log_z()
+    assert a.done() == (True, smc.FINISHED)
+    lz = a.log_z()
     b = smc.Run(model, n, 2)
     assert b.run_to_end() == smc.FINISHED
     assert b.log_z() == lz
