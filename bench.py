@@ -55,10 +55,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n_launch_bytes: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_crbd_yule256_n2p20.json")
+def measured_traffic(kernel: str, n_launch_bytes: float, record: str = "traffic_crbd_yule256_n2p20.json"):
+    """HBM bytes per launch (launches that did work) from a committed rocprofv3
+    counter summary, if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -207,6 +207,82 @@ def seir_point(smc, ctx, I, n: int = 1 << 16, days: int = 100, runs: int = 3, cp
     return out
 
 
+def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cpu: bool = True):
+    """A compiled program (Sec. 4): eq. (2)'s state-space model written as a
+    recursive CorePPL-style function, compiled by Algorithm 2 and run by the
+    bytecode interpreter, beside the hand-written built-in block table on the
+    same data (both FP64 state; they give the same bits). Every observation
+    adds one 8-word frame to the particle's stack, so at the start of round t
+    the live stack holds 3 + 8 t words and the live-prefix gather moves
+    16 (3 + 8 t) bytes per particle: the leg measures that copy against HBM."""
+    import torch
+    from paper_2112_00364_amd import ppl
+    y = I.lgssm_data(T, 2000)
+    img = ppl.compile_program(I.lgssm_program(y), stack_words=8 * T + 8)
+    out = {"workload": f"lgssm_program_T{T}_n{n}", "particles": n, "observations": T, "runs": runs,
+           "stack_words": img.stack_words, "blocks": img.n_blocks, "instructions": int(len(img.code))}
+
+    def timed(model, seed):
+        run = smc.Run(model, n, seed)
+        run.run_to_end()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(ctx.stream)
+        for i in range(runs):
+            run.reset(seed + 1 + i)
+            run.run_to_end()
+        end.record(ctx.stream)
+        torch.cuda.synchronize()
+        return run, start.elapsed_time(end) / runs
+
+    model = smc.Model(ctx, {"kind": "program", "precision": 64, "program": img})
+    run, ms = timed(model, 81)
+    s = run.stats()
+    lz_program = s["log_z"]
+    run.reset(81 + runs)
+    run.profile(True)
+    run.run_to_end()
+    kt = run.kernel_times()
+    run.profile(False)
+    run.close()
+    model.close()
+    builtin = smc.Model(ctx, I.lgssm_spec(y, 64))
+    brun, bms = timed(builtin, 81)
+    lz_builtin = brun.stats()["log_z"]
+    brun.close()
+    builtin.close()
+    ms_prop, launches = kt["propagate"]
+    # run_to_end checks termination every 16 rounds, so a run also makes a few
+    # launches after its last round (they return at once): rate the propagation
+    # by its summed time per run, i.e. per round of the run.
+    us = 1e3 * ms_prop / T
+    # per particle and round: anc 4 + block 1 + sp 4 read, block 1 + sp 4 + lw 8 written,
+    # plus the live prefix read and written (the stores of the running block are not counted)
+    words = sum(3 + 8 * t for t in range(1, T))
+    per_round = n * (22.0 * T + 16.0 * words) / T
+    out.update({"ms_per_run": ms, "builtin_ms_per_run": bms, "status": s["status"],
+                "block_steps_per_s": s["block_steps"] / (ms / 1e3),
+                "same_log_z_as_builtin": lz_program == lz_builtin,
+                "propagate_us_per_round": us, "propagate_launches_per_run": launches,
+                "roofline": {"bound": "hbm", "kernel": "propagate (interpreter + live-prefix gather)",
+                             "achieved": round(per_round / us / 1e3, 1), "peak": 8000.0, "unit": "GB/s",
+                             "frac": round(per_round / us / 1e3 / 8000.0, 4),
+                             "algorithmic_bytes_per_round": per_round,
+                             "traffic": measured_traffic("propagate_program", per_round,
+                                                         "traffic_program_lgssm100_n2p20.json")}})
+    if cpu:
+        from oracle import ppl_oracle as PO
+        m = 512
+        t0 = time.perf_counter()
+        r = PO.ProgramRun(I.lgssm_program(y), m, 81)
+        r.run_to_end()
+        dt = time.perf_counter() - t0
+        out["cpu_oracle_particle_rounds_per_s"] = m * T / dt
+        out["cpu_oracle_sample"] = f"{m} particles, all {T} observations, source-level oracle, one thread, {dt:.1f} s"
+    return out
+
+
 def crbd_ds_point(smc, ctx, I, tree, n: int, tau: float = 0.5, runs: int = 3):
     """The paper's CRBD experiment with variance-reducing techniques: the
     headline tree with static delayed sampling (rates marginalised) and
@@ -274,6 +350,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 2^24-particle point")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS-triggered point")
     ap.add_argument("--no-seir", action="store_true", help="skip the vector-borne disease (SEIR) point")
+    ap.add_argument("--no-program", action="store_true", help="skip the compiled-program point")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -401,6 +478,9 @@ def main():
     if not args.no_seir:
         print("SEIR point", file=sys.stderr, flush=True)
         out["seir"] = seir_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
+    if not args.no_program:
+        print("compiled-program point", file=sys.stderr, flush=True)
+        out["program"] = program_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
     if not args.no_large:
         print("2^24-particle point", file=sys.stderr, flush=True)
         out["large"] = large_point(smc, model, 1 << 24)

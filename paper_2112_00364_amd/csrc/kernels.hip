@@ -522,7 +522,18 @@ __device__ __forceinline__ void program_body(const RunDev& R, uint32_t tile)
         blk = kStop;
         lw = -__builtin_huge_val();
     }
-    for (uint32_t w = 0; w < sp; ++w) st[w * n + j] = st_in[w * n + src];
+    // Live-prefix gather, 16 words in flight per lane (all loads before the
+    // stores). Apart from the top frame, the copied words are read again only
+    // by the next round's gather, so the stores are non-temporal.
+    uint32_t w0 = 0;
+    for (; w0 + 16 <= sp; w0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = st_in[(uint64_t)(w0 + u) * n + src];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) __builtin_nontemporal_store(v[u], &st[(uint64_t)(w0 + u) * n + j]);
+    }
+    for (; w0 < sp; ++w0) st[(uint64_t)w0 * n + j] = st_in[(uint64_t)w0 * n + src];
 
     bool live = valid && blk != kStop;
     uint32_t pc = live ? P.block_start[blk] : 0u;

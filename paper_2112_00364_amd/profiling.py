@@ -28,6 +28,7 @@ import sqlite3
 
 # Kernel-name prefixes -> the names bench.py reports.
 KERNELS = {
+    "k_propagate_one<6": "propagate_program",
     "k_propagate": "propagate",
     "k_fold_sums": "fold_sums",
     "k_reduce": "reduce",
@@ -123,6 +124,17 @@ def calibration_scale(rows) -> float:
     return CALIBRATION_BYTES / max(copies)
 
 
+def _launch_stats(values):
+    """Mean bytes over the launches that did work. A run driven by
+    smc_run_to_end checks termination every few rounds, so it can end with
+    launches that only read the run's status; dispatches below 1% of the
+    kernel's median are counted apart as idle."""
+    med = sorted(values)[len(values) // 2]
+    busy = [v for v in values if v >= 0.01 * med]
+    return {"launches": len(busy), "idle_launches": len(values) - len(busy),
+            "bytes_per_launch": sum(busy) / len(busy)}
+
+
 def traffic(fetch_db: str, write_db: str) -> dict:
     result = {}
     for counter, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
@@ -134,13 +146,14 @@ def traffic(fetch_db: str, write_db: str) -> dict:
             if b is not None:
                 per[b].append(v * scale)
         result[counter] = {"bytes_per_counter_unit": scale,
-                           "kernels": {k: {"launches": len(v), "bytes_per_launch": sum(v) / len(v)}
-                                       for k, v in per.items()}}
+                           "kernels": {k: _launch_stats(v) for k, v in per.items()}}
     kernels = {}
     for k in result["FETCH_SIZE"]["kernels"]:
         f = result["FETCH_SIZE"]["kernels"][k]["bytes_per_launch"]
         w = result["WRITE_SIZE"]["kernels"].get(k, {}).get("bytes_per_launch", 0.0)
-        kernels[k] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w, "hbm_bytes_per_launch": f + w}
+        kernels[k] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w, "hbm_bytes_per_launch": f + w,
+                      "launches": result["FETCH_SIZE"]["kernels"][k]["launches"],
+                      "idle_launches": result["FETCH_SIZE"]["kernels"][k]["idle_launches"]}
     return {"kernels": kernels,
             "fetch_scale": result["FETCH_SIZE"]["bytes_per_counter_unit"],
             "write_scale": result["WRITE_SIZE"]["bytes_per_counter_unit"]}
