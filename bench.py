@@ -283,6 +283,47 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     return out
 
 
+def bucketing_point(smc, ctx, I, n: int = 1 << 20, T: int = 12, runs: int = 2):
+    """Block bucketing on a program whose particles resume at two different
+    blocks every round (regime_program: resampling inside the branch of a
+    random regime, 24 Gamma draws of work per branch): complete runs without
+    and with bucketing, and the autotuner's choice from a few timed rounds."""
+    import torch
+    from paper_2112_00364_amd import autotune, ppl
+    img = ppl.compile_program(I.regime_program(I.branching_observations(T, 9)), stack_words=256)
+    model = smc.Model(ctx, {"kind": "program", "precision": 64, "program": img})
+    run = smc.Run(model, n, 91)
+    out = {"workload": f"regime_program_T{T}_n{n}", "particles": n, "observations": T, "runs": runs}
+    zs = {}
+    for on in (False, True):
+        run.set_bucketing(on)
+        run.reset(91)
+        run.run_to_end()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(ctx.stream)
+        for i in range(runs):
+            run.reset(92 + i)
+            run.run_to_end()
+        end.record(ctx.stream)
+        torch.cuda.synchronize()
+        key = "on" if on else "off"
+        out[f"ms_per_run_bucketing_{key}"] = start.elapsed_time(end) / runs
+        zs[key] = run.stats()["log_z"]
+        run.reset(95)
+        run.profile(True)
+        run.run_to_end()
+        kt = run.kernel_times()
+        run.profile(False)
+        out[f"kernel_ms_per_run_bucketing_{key}"] = {k: round(v[0], 3) for k, v in kt.items()}
+    out["same_log_z"] = zs["on"] == zs["off"]
+    out["autotuner"] = autotune.choose_bucketing(run, 96, rounds=4, repeats=2)
+    run.close()
+    model.close()
+    return out
+
+
 def crbd_ds_point(smc, ctx, I, tree, n: int, tau: float = 0.5, runs: int = 3):
     """The paper's CRBD experiment with variance-reducing techniques: the
     headline tree with static delayed sampling (rates marginalised) and
@@ -351,6 +392,7 @@ def main():
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS-triggered point")
     ap.add_argument("--no-seir", action="store_true", help="skip the vector-borne disease (SEIR) point")
     ap.add_argument("--no-program", action="store_true", help="skip the compiled-program point")
+    ap.add_argument("--no-bucketing", action="store_true", help="skip the block-bucketing point")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -481,6 +523,9 @@ def main():
     if not args.no_program:
         print("compiled-program point", file=sys.stderr, flush=True)
         out["program"] = program_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
+    if not args.no_bucketing:
+        print("block-bucketing point", file=sys.stderr, flush=True)
+        out["bucketing"] = bucketing_point(smc, ctx, I)
     if not args.no_large:
         print("2^24-particle point", file=sys.stderr, flush=True)
         out["large"] = large_point(smc, model, 1 << 24)

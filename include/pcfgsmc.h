@@ -260,6 +260,19 @@ smc_status smc_log_z(smc_run* run, double* out);
  * status. */
 smc_status smc_run_to_end(smc_run* run);
 
+/* Block bucketing. Particles may sit at different blocks of the PCFG at the
+ * same time (Sec. 3.2), and lanes of one wavefront running different blocks
+ * take turns. enable = 1: before every smc_step the
+ * run's particle slots are sorted, stably, by the block each will resume at
+ * (b_stop last), and lane i of the propagation takes the i-th slot of that
+ * order, so the lanes of a wavefront mostly run the same block. Slots keep
+ * their random streams: results are bit-identical either way. Costs three
+ * small launches per round and N + 256 (N / 1024 + 1) 32-bit words of device
+ * memory (allocated on first use); pays off when particles resume at
+ * different blocks (compiled programs). Single runs only (not batches).
+ * Synchronises; a captured graph of the run is dropped and captured again. */
+smc_status smc_set_bucketing(smc_run* run, int32_t enable);
+
 /* Algorithm 1 step 1 again on the run's existing buffers, with a new seed:
  * no allocation; the next smc_run_to_end replays (capturing it the first time)
  * a graph of all rounds. */
@@ -292,7 +305,7 @@ smc_status smc_run_destroy(smc_run* run); /* NULL-safe */
 /* Per-kernel timing with HIP events recorded on the context stream around
  * every launch a run makes while profiling is on (smc_step, smc_resample,
  * smc_run_to_end). Index 0 = propagation (with the deep-stack recomputation),
- * 1 = unused, 2 = reduction (+ the fold of the tile sums for runs above 2^20
+ * 1 = block bucketing (smc_set_bucketing), 2 = reduction (+ the fold of the tile sums for runs above 2^20
  * particles), 3 = scan and ancestors (log Z, next round); ms = summed
  * durations, launches = count. smc_profile(run, 1) clears previous records;
  * both calls synchronise. */

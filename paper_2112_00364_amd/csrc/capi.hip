@@ -255,6 +255,7 @@ struct smc_run {
     // the whole lockstep run (rounds 0..R-1) captured once and replayed
     hipGraphExec_t graph = nullptr;
     uint32_t graph_rounds = 0;
+    uint32_t* perm_buf = nullptr;  // block bucketing permutation (allocated on first use)
     uint32_t resets = 0;  // a reset run is replayed from a captured graph
     hipEvent_t next_event()
     {
@@ -351,6 +352,18 @@ smc_status do_step(smc_run* r)
     if (r->known_status != SMC_OK) return r->known_status;
     hipStream_t st = r->ctx->stream;
     const int kind = r->model->kind, prec = r->model->precision;
+    if (r->host.perm) {
+        if (r->profiling) {
+            hipEvent_t a = r->next_event(), b = r->next_event();
+            if (!a || !b) return fail(SMC_ERR_DEVICE, "event creation failed");
+            HIP_TRY(hipEventRecord(a, st));
+            HIP_TRY(launch_bucket(r->host, st));
+            HIP_TRY(hipEventRecord(b, st));
+            r->timed.push_back(smc_run::Timed{1, a, b});
+        } else {
+            HIP_TRY(launch_bucket(r->host, st));
+        }
+    }
     if (r->profiling) {
         hipEvent_t a = r->next_event(), b = r->next_event();
         if (!a || !b) return fail(SMC_ERR_DEVICE, "event creation failed");
@@ -634,7 +647,8 @@ static smc_status capture_run(smc_run* r, uint32_t rounds)
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     for (uint32_t k = 0; k < rounds && e == hipSuccess; ++k) {
-        e = launch_propagate_one(r->model->kind, r->model->precision, r->host, cap);
+        if (r->host.perm) e = launch_bucket(r->host, cap);
+        if (e == hipSuccess) e = launch_propagate_one(r->model->kind, r->model->precision, r->host, cap);
         if (e == hipSuccess) e = launch_resample_one(r->host, r->dev, cap, 3);
     }
     hipError_t e2 = hipStreamEndCapture(cap, &g);
@@ -686,6 +700,33 @@ smc_status smc_run_to_end(smc_run* r)
         if (c.status != SMC_OK) return c.status;
         chunk = 16;
     }
+}
+
+smc_status smc_set_bucketing(smc_run* r, int32_t enable)
+{
+    if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    RunDev& h = r->host;
+    const bool on = enable != 0;
+    if (on && !r->perm_buf) {
+        h.bucket_hist = (uint32_t*)r->arena.get((size_t)kBuckets * h.red_tiles * sizeof(uint32_t));
+        h.bucket_total = (uint32_t*)r->arena.get((size_t)kBuckets * sizeof(uint32_t));
+        r->perm_buf = (uint32_t*)r->arena.get((size_t)r->n * sizeof(uint32_t));
+        if (!h.bucket_hist || !h.bucket_total || !r->perm_buf) {
+            h.bucket_hist = nullptr;
+            h.bucket_total = nullptr;
+            r->perm_buf = nullptr;
+            return fail(SMC_ERR_OOM, "device allocation failed for the bucketing buffers");
+        }
+    }
+    if ((h.perm != nullptr) == on) return SMC_OK;
+    h.perm = on ? r->perm_buf : nullptr;
+    HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, r->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(r->ctx->stream));
+    if (r->graph) {  // the captured launch sequence changes: capture again when next needed
+        (void)hipGraphExecDestroy(r->graph);
+        r->graph = nullptr;
+    }
+    return SMC_OK;
 }
 
 smc_status smc_reset(smc_run* r, uint64_t seed)

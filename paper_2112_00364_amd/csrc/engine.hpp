@@ -51,6 +51,12 @@ struct RunDev {
     double* part_e;                // per reduction tile: sum of exp(lw - M)
     unsigned long long* part_q2;   // per reduction tile: sum of squared grid units (lo, hi), ESS rule only
     double* prefix;                // per reduction tile: grid units before the tile (fold-kernel path)
+    // block bucketing (optional, single runs): the propagation takes slot
+    // perm[i] at position i; the counting sort that fills perm keeps its
+    // per-(block, tile) counts and per-block totals here
+    uint32_t* perm;
+    uint32_t* bucket_hist;         // [kBuckets][red_tiles], block-major
+    uint32_t* bucket_total;        // [kBuckets]
 };
 
 // Lanes (= particles) per propagation work-group, by model kind: 128 for the
@@ -66,6 +72,10 @@ constexpr int kTileRed = kRedThreads * kRedItems;  // particles per reduction ti
 // reduction's tile sums inside the scan kernel; larger runs use the
 // one-work-group fold kernel.
 constexpr uint32_t kMaxFusedRedTiles = 1024;
+// Block bucketing sorts slots by their resume block (255 = b_stop) into
+// kBuckets keys, over the reduction tiles.
+constexpr int kBuckets = 256;
+static_assert(kBuckets == kRedThreads, "one bucket per thread of a tile work-group");
 
 // Propagation work-group t folds its partial (max order-key of lw; active
 // count and block steps packed in one word) into slot t mod kPartialGroups

@@ -485,10 +485,19 @@ __device__ inline bool run_particle(const RunDev& R, const ModelDev& m, uint64_t
 // frame sizes and the capacity, and the stored return blocks, return-value
 // locations and data indices, faulting the particle (weight -inf) otherwise.
 // ---------------------------------------------------------------------------
+// Slot a propagation lane takes: its position, or the position's entry of the
+// bucketing permutation (clamped, so a malformed entry cannot leave the run).
+__device__ inline uint32_t lane_slot(const RunDev& R, uint32_t idx)
+{
+    if (!R.perm || idx >= R.n) return idx;
+    const uint32_t j = R.perm[idx];
+    return j < R.n ? j : idx;
+}
+
 template <int kThreads>
 __device__ __forceinline__ void program_body(const RunDev& R, uint32_t tile)
 {
-    const uint32_t j = tile * kThreads + threadIdx.x;
+    const uint32_t j = lane_slot(R, tile * kThreads + threadIdx.x);
     const bool valid = j < R.n;
     RunCtl* ctl = R.ctl;
     const int32_t status = uniform_i32(ctl->status);
@@ -669,7 +678,7 @@ template <int Kind, class Real>
 __device__ __forceinline__ void builtin_body(const RunDev& R, uint32_t tile)
 {
     constexpr int kThreads = prop_threads(Kind);
-    const uint32_t j = tile * kThreads + threadIdx.x;
+    const uint32_t j = lane_slot(R, tile * kThreads + threadIdx.x);
     const bool valid = j < R.n;
     RunCtl* ctl = R.ctl;
     const int32_t status = uniform_i32(ctl->status);
@@ -736,6 +745,135 @@ __global__ __launch_bounds__(prop_threads(Kind)) void k_propagate(const RunDev* 
 {
     const TileRef tr = tiles[blockIdx.x];
     propagate_body<Kind, Real>(runs[tr.run], tr.tile);
+}
+
+// ---------------------------------------------------------------------------
+// Block bucketing (optional). Before a propagation, a stable counting sort of
+// the particle slots by the block each resumes at (the ancestor's block, or
+// its own after a round that kept its weights; 255 = b_stop sorts last), so
+// the lanes of a wavefront mostly run the same block. Three launches over
+// kTileRed-slot tiles: per-tile counts (block-major), an exclusive scan of
+// each block's counts over the tiles, and a scatter that ranks every slot
+// among the equal keys before it (rows of 64 slots, ranked with ballots).
+// Slots keep their random streams, so the results do not depend on it.
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t resume_key(const RunDev& R, uint32_t j, uint32_t round, bool carry)
+{
+    if (round == 0) return 0u;
+    const ParticleBuf& in = R.buf[(round & 1u) ^ 1u];
+    return in.blk[carry ? j : R.anc[j]];
+}
+
+// Inclusive scan of one value per thread over a kRedThreads work-group.
+__device__ inline uint32_t block_incl_scan_u32(uint32_t v)
+{
+    __shared__ uint32_t s_wave[kRedThreads / 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v = wave_incl_scan<OpAddU32>(v);
+    if (lane == 63) s_wave[wave] = v;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wave; ++w) before += s_wave[w];
+    __syncthreads();
+    return v + before;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_bucket_count(const RunDev R)
+{
+    RunCtl* ctl = R.ctl;
+    if (uniform_i32(ctl->status) != 0) return;
+    const uint32_t round = uniform_u32(ctl->round);
+    const bool carry = uniform_u32(ctl->carry) != 0;
+    __shared__ uint32_t s_hist[kBuckets];
+    s_hist[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kTileRed;
+    for (int i = 0; i < kRedItems; ++i) {
+        const uint32_t j = base + threadIdx.x + i * kRedThreads;
+        if (j < R.n) atomicAdd(&s_hist[resume_key(R, j, round, carry)], 1u);
+    }
+    __syncthreads();
+    R.bucket_hist[threadIdx.x * R.red_tiles + blockIdx.x] = s_hist[threadIdx.x];
+}
+
+// One work-group per block: exclusive prefix of its counts over the tiles.
+__global__ __launch_bounds__(kRedThreads) void k_bucket_scan(const RunDev R)
+{
+    if (uniform_i32(R.ctl->status) != 0) return;
+    uint32_t* col = R.bucket_hist + (uint64_t)blockIdx.x * R.red_tiles;
+    const uint32_t T = R.red_tiles;
+    const uint32_t per = (T + kRedThreads - 1) / kRedThreads;
+    const uint32_t lo = threadIdx.x * per;
+    const uint32_t hi = lo + per < T ? lo + per : T;
+    uint32_t sum = 0;
+    for (uint32_t i = lo; i < hi; ++i) sum += col[i];
+    const uint32_t incl = block_incl_scan_u32(sum);
+    uint32_t run = incl - sum;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t v = col[i];
+        col[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == kRedThreads - 1) R.bucket_total[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_bucket_scatter(const RunDev R)
+{
+    RunCtl* ctl = R.ctl;
+    if (uniform_i32(ctl->status) != 0) return;
+    const uint32_t round = uniform_u32(ctl->round);
+    const bool carry = uniform_u32(ctl->carry) != 0;
+    constexpr int kRows = kTileRed / 64;
+    __shared__ uint32_t s_base[kBuckets];
+    __shared__ uint32_t s_row[kRows][kBuckets];
+    const uint32_t t = threadIdx.x;
+    const uint32_t tot = R.bucket_total[t];
+    const uint32_t incl = block_incl_scan_u32(tot);
+    s_base[t] = (incl - tot) + R.bucket_hist[t * R.red_tiles + blockIdx.x];
+    for (int r = 0; r < kRows; ++r) s_row[r][t] = 0;
+    __syncthreads();
+    const int wave = t >> 6, lane = t & 63;
+    constexpr int kRowsPerWave = kRows / (kRedThreads / 64);
+    uint32_t key[kRowsPerWave];
+    bool valid[kRowsPerWave];
+    for (int q = 0; q < kRowsPerWave; ++q) {
+        const int row = wave + (kRedThreads / 64) * q;
+        const uint32_t j = blockIdx.x * kTileRed + row * 64 + lane;
+        valid[q] = j < R.n;
+        key[q] = valid[q] ? resume_key(R, j, round, carry) : 0u;
+        unsigned long long todo = __ballot(valid[q]);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)key[q], leader);
+            const unsigned long long mask = __ballot(valid[q] && key[q] == lk);
+            if (lane == leader) s_row[row][lk] = (uint32_t)__popcll(mask);
+            todo &= ~mask;
+        }
+    }
+    __syncthreads();
+    uint32_t run = 0;
+    for (int r = 0; r < kRows; ++r) {
+        const uint32_t c = s_row[r][t];
+        s_row[r][t] = run;
+        run += c;
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int q = 0; q < kRowsPerWave; ++q) {
+        const int row = wave + (kRedThreads / 64) * q;
+        const uint32_t j = blockIdx.x * kTileRed + row * 64 + lane;
+        unsigned long long todo = __ballot(valid[q]);
+        while (todo) {
+            const int leader = __ffsll((long long)todo) - 1;
+            const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)key[q], leader);
+            const unsigned long long mask = __ballot(valid[q] && key[q] == lk);
+            if (valid[q] && key[q] == lk) {
+                const uint32_t pos = s_base[lk] + s_row[row][lk] + (uint32_t)__popcll(mask & below);
+                if (pos < R.n) R.perm[pos] = j;
+            }
+            todo &= ~mask;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1295,6 +1433,14 @@ hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipS
     else if (kind == 6) hipLaunchKernelGGL((k_propagate_one<6, double>), g, b, 0, st, run);
     else if (precision == 32) hipLaunchKernelGGL((k_propagate_one<5, float>), g, b, 0, st, run);
     else hipLaunchKernelGGL((k_propagate_one<5, double>), g, b, 0, st, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket(const RunDev& run, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_bucket_count, dim3(run.red_tiles), dim3(kRedThreads), 0, st, run);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(kBuckets), dim3(kRedThreads), 0, st, run);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(run.red_tiles), dim3(kRedThreads), 0, st, run);
     return hipGetLastError();
 }
 

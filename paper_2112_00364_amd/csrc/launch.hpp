@@ -12,6 +12,8 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
 // single run: the run record travels as a kernel argument
 hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipStream_t st);
 hipError_t launch_resample_one(const RunDev& run, const RunDev* run_dev, hipStream_t st, int part);
+// block bucketing: fills run.perm for the next propagation (three launches)
+hipError_t launch_bucket(const RunDev& run, hipStream_t st);
 hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, uint32_t n_runs,
                          bool any_unfused, hipStream_t st);
 hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);

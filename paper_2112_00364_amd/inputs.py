@@ -363,3 +363,36 @@ def branching_observations(T: int, seed: int) -> list:
         x = 0.9 * x + rng.normal(0.0, 0.7)
         out.append(round(x * 8.0) / 8.0)
     return out
+
+
+def regime_program(obs, draws: int = 24) -> str:
+    """A regime-switching program whose checkpoints sit inside the branches:
+    each step draws a regime, resamples inside that regime's branch, then does
+    the regime's work (`draws` Gamma draws, inlined) before observing obs[t].
+    After resampling, the particles of a wavefront resume at two different
+    blocks, so it exercises block bucketing."""
+    os_ = " ".join(_num(v) for v in obs)
+
+    def gammas(shape, scale):
+        lines = ["(let s 0)"]
+        for _ in range(draws):
+            lines += [f"(sample g gamma {_num(shape)} {_num(scale)})", "(let s (+ s g))"]
+        return "\n    ".join(lines) + "\n    (return s)"
+
+    return f"""(program
+  (data obs {os_})
+  (def work_a (x)
+    {gammas(3.0, 1.0)})
+  (def work_b (x)
+    {gammas(6.0, 0.5)})
+  (def step (t x)
+    (sample r bernoulli 0.5)
+    (if r ((resample) (call s work_a x) (let x2 (+ (* 0.5 x) (* 0.02 s))))
+          ((resample) (call s work_b x) (let x2 (- (* 0.5 x) (* 0.02 s)))))
+    (observe normal (at obs t) x2 1.0)
+    (if (< (+ t 1) (len obs)) ((call u step (+ t 1) x2)) ((let u 0)))
+    (return u))
+  (def main ()
+    (sample x0 normal 0 1)
+    (call u step 0 x0)
+    (return u)))"""

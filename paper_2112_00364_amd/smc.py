@@ -136,6 +136,7 @@ def lib():
         "smc_log_z": [vp, C.POINTER(C.c_double)],
         "smc_run_to_end": [vp],
         "smc_reset": [vp, u64],
+        "smc_set_bucketing": [vp, i32],
         "smc_read": [vp, i32, vp, C.c_size_t],
         "smc_run_stats": [vp, C.POINTER(_Stats)],
         "smc_run_destroy": [vp],
@@ -316,6 +317,10 @@ class Run:
     def reset(self, seed: int):
         _check(lib().smc_reset(self._h, int(seed)))
 
+    def set_bucketing(self, enable: bool = True):
+        """Sort particle slots by resume block before each propagation (results unchanged)."""
+        _check(lib().smc_set_bucketing(self._h, 1 if enable else 0))
+
     def stats(self):
         s = _Stats()
         _check(lib().smc_run_stats(self._h, C.byref(s)))
@@ -326,10 +331,11 @@ class Run:
         _check(lib().smc_profile(self._h, 1 if enable else 0))
 
     def kernel_times(self):
-        """{kernel: (total ms, launches)} for propagate, deep+fold_max, reduce+fold_sums, scan_anc."""
+        """{kernel: (total ms, launches)} for propagate, bucketing (three launches per
+        entry), reduce (+ fold_sums) and scan_anc."""
         t = _KernelTimes()
         _check(lib().smc_profile_read(self._h, C.byref(t)))
-        names = ("propagate", "unused", "reduce", "scan_anc")
+        names = ("propagate", "bucket", "reduce", "scan_anc")
         return {names[i]: (t.ms[i], int(t.launches[i])) for i in range(4)}
 
     def _read(self, what, dtype, count=1):
