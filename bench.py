@@ -212,15 +212,18 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     recursive CorePPL-style function, compiled by Algorithm 2 and run by the
     bytecode interpreter, beside the hand-written built-in block table on the
     same data (both FP64 state; they give the same bits). Every observation
-    adds one 8-word frame to the particle's stack, so at the start of round t
-    the live stack holds 3 + 8 t words and the live-prefix gather moves
-    16 (3 + 8 t) bytes per particle: the leg measures that copy against HBM."""
+    adds one frame of `step` to the particle's stack, so at the start of round
+    t the live stack holds F_main + t F_step words and the live-prefix gather
+    moves 16 (F_main + t F_step) bytes per particle: the leg measures that copy
+    against HBM."""
     import torch
     from paper_2112_00364_amd import ppl
     y = I.lgssm_data(T, 2000)
     img = ppl.compile_program(I.lgssm_program(y), stack_words=8 * T + 8)
+    f_main, f_step = img.frames["main"], img.frames["step"]
     out = {"workload": f"lgssm_program_T{T}_n{n}", "particles": n, "observations": T, "runs": runs,
-           "stack_words": img.stack_words, "blocks": img.n_blocks, "instructions": int(len(img.code))}
+           "stack_words": img.stack_words, "frame_words": dict(img.frames), "blocks": img.n_blocks,
+           "instructions": int(len(img.code))}
 
     def timed(model, seed):
         run = smc.Run(model, n, seed)
@@ -259,7 +262,7 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     us = 1e3 * ms_prop / T
     # per particle and round: anc 4 + block 1 + sp 4 read, block 1 + sp 4 + lw 8 written,
     # plus the live prefix read and written (the stores of the running block are not counted)
-    words = sum(3 + 8 * t for t in range(1, T))
+    words = sum(f_main + f_step * t for t in range(1, T))
     per_round = n * (22.0 * T + 16.0 * words) / T
     out.update({"ms_per_run": ms, "builtin_ms_per_run": bms, "status": s["status"],
                 "block_steps_per_s": s["block_steps"] / (ms / 1e3),

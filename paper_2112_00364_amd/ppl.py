@@ -15,7 +15,10 @@ tool that produces them, following the compilation scheme of Sec. 4:
    kinds of eq. (3) and split into basic blocks by Algorithm 2 (`decompose`);
 5. stack frames as in Sec. 4.1: each decomposed function has a frame of
    fixed size holding its return block, the location of its return value,
-   its parameters and every local; the caller allocates the whole frame and
+   its parameters and every local that more than one block uses (a local used
+   by a single block lives in a register of that block, as Sec. 4.1 allows;
+   call results stay in the frame, since the callee writes them there); the
+   caller allocates the whole frame and
    writes the first three parts before jumping to the callee; addresses on the
    stack are relative to the stack base, since resampling moves particles
    (Sec. 4.3);
@@ -67,6 +70,7 @@ OPS = {
 }
 TERMINATORS = {"GOTO", "CKPT", "JRET", "FAULT"}
 N_REGS = 16
+REG_LOCALS = 8  # block-local variables held in registers per block (r15 downwards)
 STOP = 255
 MAX_BLOCKS = 254
 
@@ -369,6 +373,37 @@ def _expr_vars(e, out):
     return out
 
 
+def _stmt_names(s, out):
+    """Names one statement defines or reads (an if: its condition only)."""
+    k = s[0]
+    if k in ("let", "sample", "call"):
+        out.add(s[1])
+    if k == "let":
+        _expr_vars(s[2], out)
+    elif k in ("sample", "call"):
+        for e in s[3]:
+            _expr_vars(e, out)
+    elif k == "observe":
+        for e in s[2] + [s[3]]:
+            _expr_vars(e, out)
+    elif k in ("weight", "return", "if"):
+        _expr_vars(s[1], out)
+    return out
+
+
+def _block_names(items, out):
+    for it in items:
+        if it[0] == "other":
+            _stmt_names(it[1], out)
+        elif it[0] == "call":
+            _stmt_names(it[2], out)
+        elif it[0] == "if":
+            _stmt_names(it[1], out)
+            _block_names(it[2], out)
+            _block_names(it[3], out)
+    return out
+
+
 def _check_defined(name, body, params):
     """Every name is assigned on every path before it is read."""
     def go(stmts, defined):
@@ -506,6 +541,8 @@ class _Gen:
         self.consts = []
         self.const_ix = {}
         self.arrays = list(src.data)
+        self.regs = {}          # block-local variable -> register, for the block being generated
+        self.limit = N_REGS     # expression registers are those below the first local's
 
     def const(self, v):
         key = np.float64(v).tobytes()
@@ -521,15 +558,18 @@ class _Gen:
 
     # expressions: value into register r; registers above r are scratch
     def expr(self, e, r, f, out):
-        if r >= N_REGS:
-            raise CompileError(f"{f}: expression too deep for {N_REGS} registers")
+        if r >= self.limit:
+            raise CompileError(f"{f}: expression too deep for {self.limit} registers")
         k = e[0]
         if k == "num":
             out.append(["CONST", r, 0, 0, self.const(e[1])])
         elif k == "var":
-            if e[1] not in self.slots[f]:
+            if e[1] in self.regs:
+                out.append(["MOV", r, self.regs[e[1]], 0, 0])
+            elif e[1] in self.slots[f]:
+                out.append(["LDF", r, 0, 0, self.slots[f][e[1]]])
+            else:
                 raise CompileError(f"{f}: unknown name {e[1]}")
-            out.append(["LDF", r, 0, 0, self.slots[f][e[1]]])
         elif k == "at":
             self.expr(e[2], r, f, out)
             out.append(["DATA", r, r, 0, self.array(e[1])])
@@ -546,17 +586,23 @@ class _Gen:
                 self.expr(b, r + 1, f, out)
                 out.append([SWAPPED.get(op) or BINARY[op], r, r, r + 1, 0])
 
+    def store(self, name, f, out):
+        """r0 -> variable (its register, or its frame slot)."""
+        if name in self.regs:
+            out.append(["MOV", self.regs[name], 0, 0, 0])
+        else:
+            out.append(["STF", 0, 0, 0, self.slots[f][name]])
+
     def stmt(self, s, f, out):
         k = s[0]
-        slot = self.slots[f]
         if k == "let":
             self.expr(s[2], 0, f, out)
-            out.append(["STF", 0, 0, 0, slot[s[1]]])
+            self.store(s[1], f, out)
         elif k == "sample":
             for i, e in enumerate(s[3]):
                 self.expr(e, i, f, out)
             out.append(["SAMPLE", 0, 0, 1, DISTS[s[2]][0]])
-            out.append(["STF", 0, 0, 0, slot[s[1]]])
+            self.store(s[1], f, out)
         elif k == "observe":
             for i, e in enumerate(s[2]):
                 self.expr(e, i, f, out)
@@ -633,19 +679,33 @@ def compile_program(text: str, stack_words: int = 256) -> ProgramImage:
         _check_defined(f, fn.body, fn.params)
     dec = decomposed_functions(src)
     bodies = inline(src, dec)
-    frames, slots = {}, {}
-    for f in sorted(bodies, key=lambda g: (g != "main", g)):
-        params = src.functions[f].params
-        _check_defined(f, bodies[f], params)
-        names = params + [v for v in _assigned(bodies[f]) if v not in params]
-        slots[f] = {v: 2 + i for i, v in enumerate(names)}
-        frames[f] = 2 + len(names)
     counter = itertools.count(1)
     order = sorted(bodies, key=lambda g: (g != "main", g))
     decomposed = {}
     for f in order:
+        _check_defined(f, bodies[f], src.functions[f].params)
         d = Decomposer(_kind(dec), counter)
         decomposed[f] = d.decompose(bodies[f])
+    # locals that a single block uses live in that block's registers; the rest
+    # (and parameters and call results) in the frame
+    frames, slots, block_regs = {}, {}, {}
+    for f in order:
+        params = src.functions[f].params
+        entry, blocks = decomposed[f]
+        users = {}
+        for idx, items in blocks.items():
+            for v in _block_names(items, set()):
+                users.setdefault(v, set()).add(idx)
+        results = {s[1] for s in _walk(bodies[f]) if s[0] == "call"}
+        assigned = [v for v in _assigned(bodies[f]) if v not in params]
+        in_regs = set()
+        for idx in blocks:
+            mine = [v for v in assigned if users.get(v) == {idx} and v not in results][:REG_LOCALS]
+            block_regs[idx] = {v: N_REGS - 1 - i for i, v in enumerate(mine)}
+            in_regs.update(mine)
+        names = params + [v for v in assigned if v not in in_regs]
+        slots[f] = {v: 2 + i for i, v in enumerate(names)}
+        frames[f] = 2 + len(names)
     # final numbering: 0 = start block, then each function's blocks, entry first
     block_of, names = {}, ["start"]
     for f in order:
@@ -669,6 +729,8 @@ def compile_program(text: str, stack_words: int = 256) -> ProgramImage:
         entry, blocks = decomposed[f]
         for idx in [entry] + sorted(i for i in blocks if i != entry):
             out = [["FRAME", 0, 0, 0, frames[f]]]
+            gen.regs = block_regs[idx]
+            gen.limit = N_REGS - len(gen.regs)
             gen.tstmts(blocks[idx], f, out)
             out.append(["FAULT", 0, 0, 0, 0])
             blocks_code.append(out)

@@ -127,7 +127,7 @@ def test_geometric_program_equals_builtin(smc, ctx, n):
 
 def test_lgssm_program_equals_builtin(smc, ctx):
     y = I.lgssm_data(100, 2000)
-    # one 8-word frame per observation on top of main's 3 words
+    # one frame of step per observation on top of main's
     model, _ = program_model(smc, ctx, I.lgssm_program(y), stack_words=1024)
     builtin = smc.Model(ctx, I.lgssm_spec(y, 64))
     n = 1 << 16
@@ -173,9 +173,9 @@ def test_stack_contents_match_bytecode_simulation(smc, ctx, oracle):
 
 
 def test_stack_overflow_faults_particles(smc, ctx, oracle):
-    """A stack of 12 words holds main's frame (3) and one flip frame (5) but
-    not a second flip frame: particles with two heads fault (weight -inf,
-    stopped) without touching memory beyond their stack."""
+    """A stack of 12 words holds main's frame (3) and two flip frames (4 each)
+    but not a third: particles with three heads fault (weight -inf, stopped)
+    without touching memory beyond their stack."""
     import bytecode_sim as BS
     txt = I.geometric_program(0.5, 1.2)
     model, img = program_model(smc, ctx, txt, stack_words=12)
