@@ -749,7 +749,7 @@ def compile_program(text: str, stack_words: int = 256) -> ProgramImage:
     astart = np.cumsum([0] + [len(src.data[n]) for n in gen.arrays]).astype(np.uint32)
     return ProgramImage(code=np.array(code, dtype=np.uint64), block_start=np.array(starts, dtype=np.uint32),
                         consts=np.array(gen.consts or [0.0], dtype=np.float64),
-                        data=np.array(data or [0.0], dtype=np.float64), array_start=astart,
+                        data=np.array(data, dtype=np.float64), array_start=astart,
                         stack_words=int(stack_words), block_names=names, frames=frames, entry=entries)
 
 

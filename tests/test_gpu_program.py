@@ -242,3 +242,53 @@ def test_programs_in_a_batch(smc, ctx):
     for s, want in zip(slots, alone):
         assert lz[s] == want
     b.close()
+
+
+def test_program_without_checkpoint_is_importance_sampling(smc, ctx, oracle, PO):
+    """No resample: the run ends in round 0 and log Z is the log-mean of the
+    weights (Alg. 1's final term), as in the oracle."""
+    txt = """(program (def main ()
+      (sample x normal 0 1) (observe normal x 0.5 0.7) (return x)))"""
+    model, _ = program_model(smc, ctx, txt)
+    for n in (1, 333, 4096):
+        run = smc.Run(model, n, 2)
+        ref = PO.ProgramRun(txt, n, 2)
+        rounds = lockstep(smc, run, ref, oracle, f"no checkpoint n={n}")
+        assert rounds == 0 and run.stats()["round"] == 0
+        lw = ref.lw
+        m = lw.max()
+        want = m + np.log(np.mean(np.exp(lw - m)))
+        assert abs(run.log_z() - want) <= 1e-12 * max(1.0, abs(want))
+        run.close()
+
+
+def test_empty_data_array_faults_reads(smc, ctx, oracle, PO):
+    txt = """(program (data d)
+      (def main () (let k (len d)) (weight k) (resample)
+        (sample u uniform 0 2) (if (< u 1) ((let v (at d 0)) (weight v)) ()) (return 0)))"""
+    model, _ = program_model(smc, ctx, txt)
+    run = smc.Run(model, 2000, 5)
+    ref = PO.ProgramRun(txt, 2000, 5)
+    lockstep(smc, run, ref, oracle, "empty data")
+    lw = run.lw()
+    assert np.isneginf(lw).any() and np.isfinite(lw).any()
+
+
+def test_program_at_maximum_particle_count(smc, ctx):
+    """2^24 particles (the largest run): the compiled geometric program against
+    the built-in geometric model, both on the GPU. Resampling keeps heads
+    particles alive for ~33 rounds at this size, one 4-word frame per heads:
+    200 words (2 x 2^24 x 200 x 8 B = 54 GB of stacks) leave room for 49."""
+    model, _ = program_model(smc, ctx, I.geometric_program(0.5, 1.2), stack_words=200)
+    builtin = smc.Model(ctx, I.geometric_spec(True, 0.5, 1.2))
+    n = 1 << 24
+    say("geometric program at 2^24")
+    a = smc.Run(model, n, 31)
+    assert a.run_to_end() == smc.FINISHED
+    za, ra = a.log_z(), a.stats()["round"]
+    a.close()
+    b = smc.Run(builtin, n, 31)
+    assert b.run_to_end() == smc.FINISHED
+    assert b.stats()["round"] == ra
+    assert b.log_z() == za
+    b.close()

@@ -261,10 +261,14 @@ def _enc(op, x=0, y=0, z=0, imm=0):
     return ppl.OPS[op] | (x << 8) | (y << 16) | (z << 24) | ((imm & 0xFFFFFFFF) << 32)
 
 
-@pytest.mark.parametrize("name", ["geometric", "lgssm", "hmm", "branching"])
+EMPTY_DATA = "(program (data d) (def main () (let k (len d)) (return k)))"
+
+
+@pytest.mark.parametrize("name", ["geometric", "lgssm", "hmm", "branching", "regime", "empty_data"])
 def test_compiled_programs_pass_validation(S, name):
     txt = {"geometric": I.geometric_program(0.5, 1.2), "lgssm": I.lgssm_program(I.lgssm_data(5, 1)),
-           "hmm": I.hmm_program([1, 0, 1]), "branching": I.branching_program([0.3, 0.2])}[name]
+           "hmm": I.hmm_program([1, 0, 1]), "branching": I.branching_program([0.3, 0.2]),
+           "regime": I.regime_program([0.1, 0.4]), "empty_data": EMPTY_DATA}[name]
     S.check_program(ppl.compile_program(txt))
 
 
