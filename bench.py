@@ -250,6 +250,13 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     run.profile(False)
     run.close()
     model.close()
+    # the same model written with a self tail call: constant stack, so no growing gather
+    timg = ppl.compile_program(I.lgssm_program(y, tail=True), stack_words=16)
+    tmodel = smc.Model(ctx, {"kind": "program", "precision": 64, "program": timg})
+    trun, tms = timed(tmodel, 81)
+    lz_tail = trun.stats()["log_z"]
+    trun.close()
+    tmodel.close()
     builtin = smc.Model(ctx, I.lgssm_spec(y, 64))
     brun, bms = timed(builtin, 81)
     lz_builtin = brun.stats()["log_z"]
@@ -264,7 +271,8 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     # plus the live prefix read and written (the stores of the running block are not counted)
     words = sum(f_main + f_step * t for t in range(1, T))
     per_round = n * (22.0 * T + 16.0 * words) / T
-    out.update({"ms_per_run": ms, "builtin_ms_per_run": bms, "status": s["status"],
+    out.update({"ms_per_run": ms, "builtin_ms_per_run": bms, "tail_call_ms_per_run": tms,
+                "tail_call_same_log_z": lz_tail == lz_builtin, "status": s["status"],
                 "block_steps_per_s": s["block_steps"] / (ms / 1e3),
                 "same_log_z_as_builtin": lz_program == lz_builtin,
                 "propagate_us_per_round": us, "propagate_launches_per_run": launches,

@@ -264,14 +264,19 @@ def geometric_program(p=0.5, w=1.5) -> str:
   (def main () (call n flip) (return n)))"""
 
 
-def lgssm_program(y, a=0.9, b=0.0, q=1.0, r=0.5, m0=0.0, s0=None) -> str:
+def lgssm_program(y, a=0.9, b=0.0, q=1.0, r=0.5, m0=0.0, s0=None, tail=False) -> str:
     """Eq. (2) / Fig. 4's state-space model as a recursive program: one step
     per observation, a resample between steps. Written with the built-in
     LGSSM model's operations (x' = (a x + b) + q z; weight obs_c - d^2 / (2 r^2)),
-    so at FP64 the two give the same bits."""
+    so at FP64 the two give the same bits. tail=True returns the recursive
+    call's result directly (a self tail call), otherwise 0 after it."""
     if s0 is None:
         s0 = math.sqrt(q * q / (1.0 - a * a))
     ys = " ".join(_num(v) for v in y)
+    if tail:
+        rest = "(if (< (+ t 1) (len y)) ((resample) (call u step (+ t 1) x1) (return u)) ((return 0))))"
+    else:
+        rest = "(if (< (+ t 1) (len y)) ((resample) (call u step (+ t 1) x1)) ())\n    (return 0))"
     return f"""(program
   (data y {ys})
   (def step (t x)
@@ -279,8 +284,7 @@ def lgssm_program(y, a=0.9, b=0.0, q=1.0, r=0.5, m0=0.0, s0=None) -> str:
     (let d (- (at y t) x1))
     (let c (* -0.5 (log (* 6.283185307179586476925286766559005768394 (* {_num(r)} {_num(r)})))))
     (weight (- c (/ (* d d) (* 2.0 (* {_num(r)} {_num(r)})))))
-    (if (< (+ t 1) (len y)) ((resample) (call u step (+ t 1) x1)) ())
-    (return 0))
+    {rest}
   (def main ()
     (sample x0 normal {_num(m0)} {_num(s0)})
     (call u step 0 x0)

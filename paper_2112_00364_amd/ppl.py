@@ -39,14 +39,21 @@ calls, draws and checkpoints bind names; expressions are pure):
     (resample)                     SMC checkpoint (Sec. 4.1)
     (if E (STMT ...) (STMT ...))   branch on E != 0
     (call X F E ...)               X := F(E ...)
-    (return E)                     last statement of a function body only
+    (return E)                     in tail position only: the last statement of the
+                                   body, or of a branch of an if in tail position
 
 Expressions: numbers, names, `(OP E ...)` with OP in + - * / neg < <= > >=
 == != not log exp sqrt floor, `(at NAME E)` (element E of a data array) and
 `(len NAME)`. Comparisons give 1 or 0. Distributions and their arguments:
 uniform (a, b), normal (mean, sd), exponential (rate), gamma (shape >= 1,
 scale), beta (a >= 1, b >= 1), bernoulli (p), poisson (mean), binomial (n, p);
-gamma and beta cannot be observed. A function without a final return returns 0.
+gamma and beta cannot be observed. A path without a return returns 0.
+
+Tail calls: a function that calls itself and returns the result at once
+(`(call X F ...)` then `(return X)`, in tail position) reuses its own frame:
+the arguments overwrite the parameters and control jumps back to the entry
+block, so a recursion over observations keeps a constant stack. (Alg. 2
+expresses such a call as a `call` whose next block is `return`.)
 """
 from __future__ import annotations
 
@@ -215,9 +222,8 @@ def parse(text: str) -> Source:
                 raise CompileError(f"function {name} defined twice")
             params = [_name(p, "parameter") for p in item[2]]
             body = [_stmt(s) for s in item[3:]]
-            for k, s in enumerate(body):
-                if s[0] == "return" and k != len(body) - 1:
-                    raise CompileError(f"{name}: return must be the last statement")
+            if not _returns_in_tail_only(body, True):
+                raise CompileError(f"{name}: return only in tail position")
             funcs[name] = Function(name, params, body)
         else:
             raise CompileError(f"bad program item {item!r}")
@@ -237,14 +243,44 @@ def _walk(stmts):
             yield from _walk(s[3])
 
 
-def _nested_returns(stmts):
-    """Returns inside if-branches are not allowed (return is a body's last statement)."""
-    for s in stmts:
-        if s[0] == "if":
-            for b in (s[2], s[3]):
-                if any(t[0] == "return" for t in _walk(b)):
-                    return True
-    return False
+def _returns_in_tail_only(stmts, tail):
+    """Is every return the last statement of a list in tail position?"""
+    for k, s in enumerate(stmts):
+        last = tail and k == len(stmts) - 1
+        if s[0] == "return" and not last:
+            return False
+        if s[0] == "if" and not all(_returns_in_tail_only(b, last) for b in (s[2], s[3])):
+            return False
+    return True
+
+
+def _end_paths(stmts, on_return, on_fallthrough):
+    """Rewrites how every path of a tail-position list ends: a final return
+    through on_return(expression), a final if branch by branch, anything else
+    by appending on_fallthrough()."""
+    if stmts and stmts[-1][0] == "return":
+        return stmts[:-1] + on_return(stmts[-1][1])
+    if stmts and stmts[-1][0] == "if":
+        s = stmts[-1]
+        return stmts[:-1] + [("if", s[1], _end_paths(s[2], on_return, on_fallthrough),
+                              _end_paths(s[3], on_return, on_fallthrough))]
+    return stmts + on_fallthrough()
+
+
+MAX_TAIL_ARGS = N_REGS - REG_LOCALS  # arguments are held in registers while the frame is rewritten
+
+
+def _tail_calls(f, params, stmts):
+    """`(call X f ...)` followed by `(return X)` at the end of a tail-position
+    list -> `(tailcall f ...)` (self-calls only)."""
+    if len(stmts) >= 2 and stmts[-1][0] == "return" and stmts[-2][0] == "call":
+        c = stmts[-2]
+        if c[2] == f and stmts[-1][1] == ("var", c[1]) and len(c[3]) <= MAX_TAIL_ARGS:
+            return stmts[:-2] + [("tailcall", f, c[3])]
+    if stmts and stmts[-1][0] == "if":
+        s = stmts[-1]
+        return stmts[:-1] + [("if", s[1], _tail_calls(f, params, s[2]), _tail_calls(f, params, s[3]))]
+    return stmts
 
 
 def decomposed_functions(src: Source) -> set:
@@ -334,10 +370,9 @@ def inline(src: Source, dec: set) -> dict:
                 ren = {v: tag + v for v in g.params + _assigned(g.body)}
                 out += [("let", ren[p], a) for p, a in zip(g.params, s[3])]
                 body = [_rename_stmt(t, ren) for t in g.body]
-                if body and body[-1][0] == "return":
-                    body = body[:-1] + [("let", s[1], body[-1][1])]
-                else:
-                    body = body + [("let", s[1], ("num", 0.0))]
+                target = s[1]
+                body = _end_paths(body, lambda e, t=target: [("let", t, e)],
+                                  lambda t=target: [("let", t, ("num", 0.0))])
                 out += expand(body)
             elif s[0] == "if":
                 out.append(("if", s[1], expand(s[2]), expand(s[3])))
@@ -348,16 +383,8 @@ def inline(src: Source, dec: set) -> dict:
     result = {}
     for f in src.functions:
         if f in dec:
-            fn = src.functions[f]
-            if _nested_returns(fn.body):
-                raise CompileError(f"{f}: return inside an if branch")
-            body = expand(fn.body)
-            if not body or body[-1][0] != "return":
-                body = body + [("return", ("num", 0.0))]
-            result[f] = body
-    for f, fn in src.functions.items():
-        if f not in dec and _nested_returns(fn.body):
-            raise CompileError(f"{f}: return inside an if branch")
+            body = expand(src.functions[f].body)
+            result[f] = _end_paths(body, lambda e: [("return", e)], lambda: [("return", ("num", 0.0))])
     return result
 
 
@@ -388,6 +415,9 @@ def _stmt_names(s, out):
             _expr_vars(e, out)
     elif k in ("weight", "return", "if"):
         _expr_vars(s[1], out)
+    elif k == "tailcall":
+        for e in s[2]:
+            _expr_vars(e, out)
     return out
 
 
@@ -420,6 +450,9 @@ def _check_defined(name, body, params):
                     _expr_vars(e, used)
             elif k == "if":
                 _expr_vars(s[1], used)
+            elif k == "tailcall":
+                for e in s[2]:
+                    _expr_vars(e, used)
             missing = used - defined
             if missing:
                 raise CompileError(f"{name}: {sorted(missing)[0]} may be read before it is assigned")
@@ -628,6 +661,18 @@ class _Gen:
                 out.append(["CKPT", 0, 0, 0, self.block_of[it[1]]])
             elif k == "call":
                 s = it[2]
+                if s[0] == "tailcall":
+                    # self tail call: arguments to registers, then over the
+                    # parameters, and back to the entry block with the same frame
+                    if it[1] != RETURN:
+                        raise CompileError("internal: tail call not in tail position")
+                    params = self.src.functions[f].params
+                    for i, e in enumerate(s[2]):
+                        self.expr(e, i, f, out)
+                    for i, p in enumerate(params):
+                        out.append(["STF", i, 0, 0, self.slots[f][p]])
+                    out.append(["GOTO", 0, 0, 0, self.entries[f]])
+                    continue
                 if it[1] == RETURN:
                     raise CompileError("internal: tail call")
                 g, fr = s[2], self.frames[s[2]]
@@ -664,7 +709,7 @@ def _kind(dec):
     def kind(s):
         if s[0] == "resample":
             return "checkpoint"
-        if s[0] == "call":
+        if s[0] in ("call", "tailcall"):
             return "call"  # inlining left only calls of decomposed functions
         if s[0] == "if":
             return "if"
@@ -679,6 +724,8 @@ def compile_program(text: str, stack_words: int = 256) -> ProgramImage:
         _check_defined(f, fn.body, fn.params)
     dec = decomposed_functions(src)
     bodies = inline(src, dec)
+    for f in bodies:
+        bodies[f] = _tail_calls(f, src.functions[f].params, bodies[f])
     counter = itertools.count(1)
     order = sorted(bodies, key=lambda g: (g != "main", g))
     decomposed = {}
@@ -751,6 +798,15 @@ def compile_program(text: str, stack_words: int = 256) -> ProgramImage:
                         consts=np.array(gen.consts or [0.0], dtype=np.float64),
                         data=np.array(data, dtype=np.float64), array_start=astart,
                         stack_words=int(stack_words), block_names=names, frames=frames, entry=entries)
+
+
+def decode_op(word: int):
+    """(opcode name, x, y, z, signed immediate) of one instruction word."""
+    inv = {v: name for name, v in OPS.items()}
+    imm = word >> 32
+    if imm >= 1 << 31:
+        imm -= 1 << 32
+    return inv.get(word & 255, word & 255), (word >> 8) & 255, (word >> 16) & 255, (word >> 24) & 255, imm
 
 
 def disassemble(img: ProgramImage) -> str:

@@ -51,6 +51,7 @@ def PO(oracle):
 
 PROGRAMS = {
     "geometric": lambda: I.geometric_program(0.5, 1.2),
+    "lgssm_tail": lambda: I.lgssm_program(I.lgssm_data(16, 2000), tail=True),
     "lgssm": lambda: I.lgssm_program(I.lgssm_data(16, 2000)),
     "hmm": lambda: I.hmm_program(I.hmm_observations(14, 7)),
     "branching": lambda: I.branching_program(I.branching_observations(7, 8)),
@@ -98,7 +99,7 @@ def lockstep(smc, run, ref, oracle, label):
 @pytest.mark.parametrize("name", list(PROGRAMS))
 @pytest.mark.parametrize("n", [1, 1000, 4099])
 def test_program_matches_oracle(smc, ctx, oracle, PO, name, n):
-    if name in ("lgssm", "branching") and n == 4099:
+    if name in ("lgssm", "lgssm_tail", "branching") and n == 4099:
         n = 2051  # the pure-Python oracle sets the size
     txt = PROGRAMS[name]()
     model, _ = program_model(smc, ctx, txt)
@@ -143,6 +144,32 @@ def test_lgssm_program_equals_builtin(smc, ctx):
         assert sa == sb
         if sa != smc.OK:
             break
+    assert a.log_z() == b.log_z()
+
+
+def test_tail_recursive_program_equals_builtin_with_constant_stack(smc, ctx):
+    """The eq. (2) program in tail form: same bits as the built-in model, and
+    every particle's stack pointer stays at main's frame plus one step frame."""
+    y = I.lgssm_data(100, 2000)
+    model, img = program_model(smc, ctx, I.lgssm_program(y, tail=True), stack_words=16)
+    builtin = smc.Model(ctx, I.lgssm_spec(y, 64))
+    n = 1 << 16
+    a = smc.Run(model, n, 9)
+    b = smc.Run(builtin, n, 9)
+    depth = img.frames["main"] + img.frames["step"]
+    for r in range(100):
+        a.step()
+        b.step()
+        if r % 33 == 0 or r == 99:
+            say("tail program vs built-in round", r)
+            assert np.array_equal(bits(a.lw()), bits(b.lw()))
+            sp = a.field(0, np.int32)
+            assert ((sp == depth) | (a.blk() == 255)).all()
+        a.resample()
+        b.resample()
+        if a.done()[0]:
+            break
+    assert a.done() == b.done() == (True, smc.FINISHED)
     assert a.log_z() == b.log_z()
 
 

@@ -211,13 +211,13 @@ def test_algorithm2_preserves_execution_order(seed):
 @pytest.mark.parametrize("text,msg", [
     ("(program (def main () (return x)))", "read before"),
     ("(program (def main () (if 1 ((let a 1)) ()) (return a)))", "read before"),
-    ("(program (def main () (return 1) (let a 2)))", "last statement"),
+    ("(program (def main () (return 1) (let a 2)))", "tail position"),
+    ("(program (def main () (if 1 ((return 1)) ()) (let a 2)))", "tail position"),
     ("(program (def main () (call a nope)))", "unknown function"),
     ("(program (def f (p) (return p)) (def main () (call a f 1 2)))", "wrong number"),
     ("(program (def main (x) (return x)))", "main"),
     ("(program (def main () (sample a normal 0)))", "bad sample"),
     ("(program (def main () (observe gamma 1 1 1)))", "bad observe"),
-    ("(program (def f () (if 1 ((return 1)) ((return 2)))) (def main () (call a f)))", "inside an if"),
     ("(program (def main () (let a (at nothere 0))))", "unknown data"),
     ("(program (def main () (let a (+ 1 2 3))))", "two operands"),
 ])
@@ -233,6 +233,29 @@ def test_frames_and_inlining():
     # depth_sum is resample-free but recursive: it keeps a frame on the stack
     assert img.frames["depth_sum"] == 2 + 4  # ra, return slot, d, s, u, r
     assert img.entry["main"] == 1 and img.block_names[0] == "start"
+
+
+def test_self_tail_calls_reuse_the_frame(oracle):
+    """A self-recursive call whose result is returned at once becomes a jump
+    to the entry block with the parameters rewritten: the stack stays at
+    main's frame plus one frame, and the results do not change."""
+    import bytecode_sim as BS
+    y = I.lgssm_data(30, 2000)
+    plain = ppl.compile_program(I.lgssm_program(y), 512)
+    tail = ppl.compile_program(I.lgssm_program(y, tail=True), 512)
+    runs = [BS.SimRun(img, 64, 5) for img in (plain, tail)]
+    depth = [0, 0]
+    while runs[0].status == oracle.OK:
+        for i, r in enumerate(runs):
+            r.step()
+            depth[i] = max(depth[i], max(q[1] for q in r.p))
+            r.resample()
+        assert np.array_equal(runs[0].anc, runs[1].anc)
+    assert runs[0].log_z == runs[1].log_z
+    assert depth[1] == tail.frames["main"] + tail.frames["step"]
+    assert depth[0] == plain.frames["main"] + 29 * plain.frames["step"]  # T - 1 nested frames at the last step
+    step_code = [ppl.decode_op(int(w)) for w in tail.code[int(tail.block_start[tail.entry["step"]]):]]
+    assert "CALLFRAME" not in {op for op, *_ in step_code}
 
 
 def test_program_too_deep_for_registers():
@@ -357,8 +380,19 @@ def test_validation_rejects_jump_into_open_frame(S):
 
 # --- compiled bytecode against the source-level oracle ------------------------------
 
+SIGN_PROGRAM = """(program
+  (def sgn (v) (if (< v 0) ((return -1)) ((if (> v 1) ((return 2)) ()))))
+  (def walk (t x)
+    (sample z normal 0 1)
+    (call s sgn (+ x z))
+    (weight (* 0.3 s))
+    (if (< t 5) ((resample) (call u walk (+ t 1) (+ x z)) (return u)) ((return x))))
+  (def main () (call r walk 0 0.0) (return r)))"""
+
 PROGRAMS = {
     "geometric": (lambda: I.geometric_program(0.5, 1.2), 64),
+    "lgssm_tail": (lambda: I.lgssm_program(I.lgssm_data(12, 2000), tail=True), 96),
+    "returns_in_branches": (lambda: SIGN_PROGRAM, 64),
     "lgssm": (lambda: I.lgssm_program(I.lgssm_data(12, 2000)), 96),
     "hmm": (lambda: I.hmm_program(I.hmm_observations(10, 7)), 64),
     "branching": (lambda: I.branching_program(I.branching_observations(6, 8)), 96),
