@@ -260,6 +260,18 @@ smc_status smc_log_z(smc_run* run, double* out);
  * status. */
 smc_status smc_run_to_end(smc_run* run);
 
+/* Checkpoint and resume. smc_snapshot copies a run's complete state between
+ * calls (control block with round, log Z and status, both particle buffers,
+ * log-weights, ancestors, auxiliary stacks, and where the run stands in
+ * Algorithm 1's step/resample alternation) to a caller-owned host buffer: with
+ * host_dst NULL it only stores the size needed in *bytes. smc_restore loads
+ * such a snapshot into a run of the same model kind, precision and particle
+ * count (a fresh smc_init, or the same run later), after which the run
+ * continues exactly as the snapshotted one would have. Both synchronise;
+ * a snapshot of another shape is rejected with SMC_ERR_INVALID. */
+smc_status smc_snapshot(smc_run* run, void* host_dst, size_t* bytes);
+smc_status smc_restore(smc_run* run, const void* host_src, size_t bytes);
+
 /* Block bucketing. Particles may sit at different blocks of the PCFG at the
  * same time (Sec. 3.2), and lanes of one wavefront running different blocks
  * take turns. enable = 1: before every smc_step the

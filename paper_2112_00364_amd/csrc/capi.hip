@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "pcfgsmc.h"
@@ -700,6 +701,89 @@ smc_status smc_run_to_end(smc_run* r)
         if (c.status != SMC_OK) return c.status;
         chunk = 16;
     }
+}
+
+// Device regions holding a run's state between calls: the control block, both
+// particle buffers, log-weights, ancestors, ClaDS side stacks and the group
+// slots the next propagation folds into (cleared by the previous scan).
+// Reduction partials are rewritten before every read, so they are not state.
+static std::vector<std::pair<void*, size_t>> state_regions(const smc_run* r)
+{
+    const smc_model* m = r->model;
+    const RunDev& h = r->host;
+    const size_t n = r->n, rb = real_bytes(m);
+    std::vector<std::pair<void*, size_t>> out;
+    out.push_back({h.ctl, sizeof(RunCtl)});
+    for (int b = 0; b < 2; ++b) {
+        out.push_back({h.buf[b].blk, n});
+        for (int f = 0; f < real_fields(m->kind); ++f) out.push_back({h.buf[b].real[f], n * rb});
+        for (int f = 0; f < stored_int_fields(m->kind); ++f) out.push_back({h.buf[b].ints[f], n * 4});
+        if (h.buf[b].stack) out.push_back({h.buf[b].stack, n * rb * (size_t)m->stack_depth});
+    }
+    out.push_back({h.lw, n * 8});
+    out.push_back({h.anc, n * 4});
+    if (h.side_stack) out.push_back({h.side_stack, (size_t)kMaxDepthCap * n * 17});
+    out.push_back({h.groups, sizeof(GroupPartials)});
+    return out;
+}
+
+struct SnapshotHeader {
+    uint64_t magic, bytes, n;
+    int32_t kind, precision, stack_depth, known_status;
+    uint32_t rounds_issued, expect_step;
+};
+constexpr uint64_t kSnapshotMagic = 0x31746e7370636d73ull;  // "smcpsnt1"
+
+smc_status smc_snapshot(smc_run* r, void* host_dst, size_t* bytes)
+{
+    if (!r || !bytes) return fail(SMC_ERR_INVALID, "NULL argument");
+    const auto regions = state_regions(r);
+    size_t need = sizeof(SnapshotHeader);
+    for (const auto& g : regions) need += g.second;
+    if (!host_dst) {
+        *bytes = need;
+        return SMC_OK;
+    }
+    if (*bytes < need) return fail(SMC_ERR_INVALID, "snapshot buffer too small");
+    SnapshotHeader hd{kSnapshotMagic, need, r->n, r->model->kind, r->model->precision, r->model->stack_depth,
+                      r->known_status, r->rounds_issued, r->expect_step ? 1u : 0u};
+    std::memcpy(host_dst, &hd, sizeof hd);
+    char* p = static_cast<char*>(host_dst) + sizeof hd;
+    hipStream_t st = r->ctx->stream;
+    for (const auto& g : regions) {
+        HIP_TRY(hipMemcpyAsync(p, g.first, g.second, hipMemcpyDeviceToHost, st));
+        p += g.second;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    *bytes = need;
+    return SMC_OK;
+}
+
+smc_status smc_restore(smc_run* r, const void* host_src, size_t bytes)
+{
+    if (!r || !host_src) return fail(SMC_ERR_INVALID, "NULL argument");
+    if (bytes < sizeof(SnapshotHeader)) return fail(SMC_ERR_INVALID, "not a snapshot");
+    SnapshotHeader hd;
+    std::memcpy(&hd, host_src, sizeof hd);
+    const auto regions = state_regions(r);
+    size_t need = sizeof(SnapshotHeader);
+    for (const auto& g : regions) need += g.second;
+    if (hd.magic != kSnapshotMagic || hd.bytes != need || bytes < need)
+        return fail(SMC_ERR_INVALID, "not a snapshot of a run of this size");
+    if (hd.n != r->n || hd.kind != r->model->kind || hd.precision != r->model->precision ||
+        hd.stack_depth != r->model->stack_depth)
+        return fail(SMC_ERR_INVALID, "snapshot taken from a run of another model or particle count");
+    const char* p = static_cast<const char*>(host_src) + sizeof hd;
+    hipStream_t st = r->ctx->stream;
+    for (const auto& g : regions) {
+        HIP_TRY(hipMemcpyAsync(g.first, p, g.second, hipMemcpyHostToDevice, st));
+        p += g.second;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    r->rounds_issued = hd.rounds_issued;
+    r->expect_step = hd.expect_step != 0;
+    r->known_status = hd.known_status;
+    return SMC_OK;
 }
 
 smc_status smc_set_bucketing(smc_run* r, int32_t enable)

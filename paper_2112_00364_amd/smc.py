@@ -137,6 +137,8 @@ def lib():
         "smc_run_to_end": [vp],
         "smc_reset": [vp, u64],
         "smc_set_bucketing": [vp, i32],
+        "smc_snapshot": [vp, vp, C.POINTER(C.c_size_t)],
+        "smc_restore": [vp, vp, C.c_size_t],
         "smc_read": [vp, i32, vp, C.c_size_t],
         "smc_run_stats": [vp, C.POINTER(_Stats)],
         "smc_run_destroy": [vp],
@@ -316,6 +318,19 @@ class Run:
 
     def reset(self, seed: int):
         _check(lib().smc_reset(self._h, int(seed)))
+
+    def snapshot(self) -> bytes:
+        """The run's complete state as bytes (checkpoint)."""
+        size = C.c_size_t(0)
+        _check(lib().smc_snapshot(self._h, None, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        _check(lib().smc_snapshot(self._h, C.cast(buf, C.c_void_p), C.byref(size)))
+        return buf.raw[:size.value]
+
+    def restore(self, snap: bytes):
+        """Load a snapshot of a run of the same model and size (resume)."""
+        buf = C.create_string_buffer(snap, len(snap))
+        _check(lib().smc_restore(self._h, C.cast(buf, C.c_void_p), len(snap)))
 
     def set_bucketing(self, enable: bool = True):
         """Sort particle slots by resume block before each propagation (results unchanged)."""
