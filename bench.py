@@ -48,10 +48,14 @@ def bytes_per_launch(kernel: str, n: int, rounds: int) -> float:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code's sources (kernels.hip and the headers it
+    includes); the host engine (capi.hip) does not change what a kernel moves,
+    so counter records stay valid across host-only changes."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2112_00364_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+        if f == "kernels.hip" or f.endswith(".hpp"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
