@@ -13,6 +13,8 @@
  *                            estimate of the RootPPL engine              Sec. 3.3
  *   smc_done            <->  the engine's termination check            Sec. 3.3
  *   smc_log_z           <->  the normalising-constant estimate          Sec. 3.3
+ *   SMC_MODEL_PROGRAM   <->  a PCFG compiled from a program (Algorithm 2,
+ *                            explicit call-stack frames)                 Sec. 4
  *
  * Conventions
  *  - Every handle is opaque. Every function returns an smc_status; no C++
@@ -24,8 +26,9 @@
  *    the matching destroy call.
  *  - Work is enqueued on the context's HIP stream and runs asynchronously.
  *    smc_done, smc_log_z, smc_read, smc_run_stats, smc_batch_poll,
- *    smc_resample_weights, the self-tests and the destroy calls synchronise
- *    with that stream.
+ *    smc_resample_weights, smc_snapshot, smc_restore, smc_set_bucketing, the
+ *    self-tests and the destroy calls synchronise with that stream.
+ *    smc_program_check needs no device at all.
  *  - Runs are deterministic: the same model, particle count and seed give the
  *    same ancestors, block indices and states, alone or inside a batch.
  *
