@@ -211,7 +211,8 @@ def seir_point(smc, ctx, I, n: int = 1 << 16, days: int = 100, runs: int = 3, cp
     return out
 
 
-def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cpu: bool = True):
+def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cpu: bool = True,
+                  tail: bool = True):
     """A compiled program (Sec. 4): eq. (2)'s state-space model written as a
     recursive CorePPL-style function, compiled by Algorithm 2 and run by the
     bytecode interpreter, beside the hand-written built-in block table on the
@@ -255,12 +256,14 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     run.close()
     model.close()
     # the same model written with a self tail call: constant stack, so no growing gather
-    timg = ppl.compile_program(I.lgssm_program(y, tail=True), stack_words=16)
-    tmodel = smc.Model(ctx, {"kind": "program", "precision": 64, "program": timg})
-    trun, tms = timed(tmodel, 81)
-    lz_tail = trun.stats()["log_z"]
-    trun.close()
-    tmodel.close()
+    tms = lz_tail = None
+    if tail:
+        timg = ppl.compile_program(I.lgssm_program(y, tail=True), stack_words=16)
+        tmodel = smc.Model(ctx, {"kind": "program", "precision": 64, "program": timg})
+        trun, tms = timed(tmodel, 81)
+        lz_tail = trun.stats()["log_z"]
+        trun.close()
+        tmodel.close()
     builtin = smc.Model(ctx, I.lgssm_spec(y, 64))
     brun, bms = timed(builtin, 81)
     lz_builtin = brun.stats()["log_z"]
@@ -276,7 +279,8 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     words = sum(f_main + f_step * t for t in range(1, T))
     per_round = n * (22.0 * T + 16.0 * words) / T
     out.update({"ms_per_run": ms, "builtin_ms_per_run": bms, "tail_call_ms_per_run": tms,
-                "tail_call_same_log_z": lz_tail == lz_builtin, "status": s["status"],
+                "tail_call_same_log_z": None if lz_tail is None else lz_tail == lz_builtin,
+                "status": s["status"],
                 "block_steps_per_s": s["block_steps"] / (ms / 1e3),
                 "same_log_z_as_builtin": lz_program == lz_builtin,
                 "propagate_us_per_round": us, "propagate_launches_per_run": launches,
@@ -408,6 +412,8 @@ def main():
     ap.add_argument("--no-seir", action="store_true", help="skip the vector-borne disease (SEIR) point")
     ap.add_argument("--no-program", action="store_true", help="skip the compiled-program point")
     ap.add_argument("--no-bucketing", action="store_true", help="skip the block-bucketing point")
+    ap.add_argument("--no-tail-call", action="store_true",
+                    help="compiled-program point: skip the tail-call form (profiles of the stack-growing form)")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
@@ -537,7 +543,7 @@ def main():
         out["seir"] = seir_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
     if not args.no_program:
         print("compiled-program point", file=sys.stderr, flush=True)
-        out["program"] = program_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
+        out["program"] = program_point(smc, ctx, I, cpu=not args.no_cpu_baseline, tail=not args.no_tail_call)
     if not args.no_bucketing:
         print("block-bucketing point", file=sys.stderr, flush=True)
         out["bucketing"] = bucketing_point(smc, ctx, I)
