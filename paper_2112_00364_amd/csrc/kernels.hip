@@ -519,6 +519,10 @@ __device__ __forceinline__ void program_body(const RunDev& R, uint32_t tile)
     double* __restrict__ st = static_cast<double*>(out.stack);
     const double* __restrict__ st_in = static_cast<const double*>(in.stack);
     double* __restrict__ reg = s_reg + threadIdx.x;  // register r at reg[r * kThreads]
+    // The bytecode is read-only for the whole launch: in the constant address
+    // space its wavefront-uniform reads can be scalar loads.
+    using ConstWord = const __attribute__((address_space(4))) unsigned long long;
+    ConstWord* code = (ConstWord*)P.code;
 
     uint32_t blk = kStop, sp = 0;
     double lw = lw0;
@@ -552,11 +556,18 @@ __device__ __forceinline__ void program_body(const RunDev& R, uint32_t tile)
     for (;;) {
         const uint32_t sel = wave_min_u32(live ? pc : 0xffffffffu);
         if (sel == 0xffffffffu) break;  // uniform: no lane of the wavefront is running
-        if (!(live && pc == sel)) continue;
-        const unsigned long long word = P.code[sel];
+        // The fetch address must stay the wavefront-uniform sel: under the
+        // branch on pc == sel the compiler would otherwise substitute the
+        // lane's own pc and fetch and decode per lane. An empty asm statement
+        // with a scalar-register operand makes the copy opaque, so the word
+        // comes by one scalar load and the dispatch below is scalar.
+        uint32_t at = sel;
+        asm volatile("" : "+s"(at));
+        const unsigned long long word = code[at];
         const uint32_t lo = (uint32_t)word;
         const uint32_t op = lo & 255u, x = (lo >> 8) & 255u, y = (lo >> 16) & 255u, z = lo >> 24;
         const uint32_t imm = (uint32_t)(word >> 32);
+        if (!(live && pc == sel)) continue;
         double* rx = reg + x * kThreads;
         const double ry = reg[y * kThreads], rz = reg[z * kThreads];
         pc = sel + 1;
