@@ -302,6 +302,44 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
     return out
 
 
+def crbd_program_point(smc, ctx, I, tree, n: int = 1 << 20, runs: int = 2):
+    """The Appendix CRBD model compiled from source (Sec. 4's path: static
+    analysis, Alg. 2, frames, bytecode) on the headline tree, to set beside the
+    built-in block table (the hand-written counterpart, as the paper sets
+    compiled CorePPL beside RootPPL). Same model, other draws: the two log Z
+    estimates agree within Monte Carlo error."""
+    import torch
+    from paper_2112_00364_amd import ppl
+    img = ppl.compile_program(I.crbd_program(tree), stack_words=1024)
+    model = smc.Model(ctx, {"kind": "program", "precision": 64, "program": img})
+    run = smc.Run(model, n, 101)
+    run.run_to_end()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    zs = []
+    for i in range(runs):
+        run.reset(102 + i)
+        run.run_to_end()
+        zs.append(run.log_z())
+    end.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / runs
+    s = run.stats()
+    run.reset(110)
+    run.profile(True)
+    run.run_to_end()
+    kt = run.kernel_times()
+    run.profile(False)
+    run.close()
+    model.close()
+    return {"workload": f"crbd_program_yule{len(tree['age']) // 2 + 1}_n{n}", "particles": n, "runs": runs,
+            "blocks": img.n_blocks, "instructions": int(len(img.code)), "frame_words": dict(img.frames),
+            "stack_words": img.stack_words, "ms_per_run": ms, "status": s["status"], "rounds": s["round"],
+            "log_z": zs, "kernel_ms_per_run": {k: round(v[0], 3) for k, v in kt.items()}}
+
+
 def bucketing_point(smc, ctx, I, n: int = 1 << 20, T: int = 12, runs: int = 2):
     """Block bucketing on a program whose particles resume at two different
     blocks every round (regime_program: resampling inside the branch of a
@@ -412,6 +450,7 @@ def main():
     ap.add_argument("--no-seir", action="store_true", help="skip the vector-borne disease (SEIR) point")
     ap.add_argument("--no-program", action="store_true", help="skip the compiled-program point")
     ap.add_argument("--no-bucketing", action="store_true", help="skip the block-bucketing point")
+    ap.add_argument("--no-crbd-program", action="store_true", help="skip the compiled CRBD point")
     ap.add_argument("--no-tail-call", action="store_true",
                     help="compiled-program point: skip the tail-call form (profiles of the stack-growing form)")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
@@ -544,6 +583,11 @@ def main():
     if not args.no_program:
         print("compiled-program point", file=sys.stderr, flush=True)
         out["program"] = program_point(smc, ctx, I, cpu=not args.no_cpu_baseline, tail=not args.no_tail_call)
+    if not args.no_crbd_program:
+        print("compiled CRBD point", file=sys.stderr, flush=True)
+        out["crbd_program"] = crbd_program_point(smc, ctx, I, tree)
+        out["crbd_program"]["builtin_ms_per_run"] = ms_per_step
+        out["crbd_program"]["builtin_log_z"] = log_zs
     if not args.no_bucketing:
         print("block-bucketing point", file=sys.stderr, flush=True)
         out["bucketing"] = bucketing_point(smc, ctx, I)

@@ -400,3 +400,68 @@ def regime_program(obs, draws: int = 24) -> str:
     (sample x0 normal 0 1)
     (call u step 0 x0)
     (return u)))"""
+
+
+def crbd_program(tree, rho=1.0, scale_lambda=1.0, scale_mu=0.5, fixed=None) -> str:
+    """The CRBD model of the Appendix listing as a CorePPL-style program for
+    the compiler: priors lambda ~ Gamma(1, scale_lambda), mu ~ Gamma(1, scale_mu)
+    (or fixed (lambda, mu)), the correction weight (n - 1) log 2 - log n!, then a
+    walk over the tree (preorder, left subtree first) that weighs every branch
+    by its survival, the observed speciation or tip, and the hidden
+    speciations that must go undetected, with a resample after each branch.
+    The tree is data: left/right children (-1 at tips) and ages."""
+    left = " ".join(str(int(v)) for v in tree["left"])
+    right = " ".join(str(int(v)) for v in tree["right"])
+    age = " ".join(_num(v) for v in tree["age"])
+    tips = sum(1 for v in tree["left"] if v < 0)
+    if fixed is None:
+        prior = (f"(sample lam gamma 1.0 {_num(scale_lambda)})\n"
+                 f"    (sample mu gamma 1.0 {_num(scale_mu)})")
+    else:
+        prior = f"(let lam {_num(fixed[0])})\n    (let mu {_num(fixed[1])})"
+    return f"""(program
+  (data left {left})
+  (data right {right})
+  (data age {age})
+  (def iter (n start blen lam mu rho)
+    (if (== n 0) ((return 1))
+        ((sample et uniform (- start blen) start)
+         (call u undetected et lam mu rho)
+         (if u ((call r iter (- n 1) start blen lam mu rho) (return r)) ((return 0))))))
+  (def undetected (start lam mu rho)
+    (sample dur exponential mu)
+    (if (> dur start) ((sample b bernoulli rho) (let c b)) ((let c 0)))
+    (if c ((return 0))
+        ((if (< dur start) ((let bl dur)) ((let bl start)))
+         (sample n poisson (* lam bl))
+         (call r iter n start bl lam mu rho)
+         (return r))))
+  (def simbranch (n start stop lam mu rho)
+    (if (== n 0) ((return 0))
+        ((sample ct uniform stop start)
+         (call u undetected ct lam mu rho)
+         (if u ((call v simbranch (- n 1) start stop lam mu rho) (return (+ v (log 2))))
+               ((return (neg inf)))))))
+  (def simtree (node parent lam mu rho)
+    (let lp1 (* (neg mu) (- (at age parent) (at age node))))
+    (if (>= (at left node) 0) ((let lp2 (log lam))) ((let lp2 (log rho))))
+    (let st (at age parent))
+    (let sp (at age node))
+    (sample n poisson (* lam (- st sp)))
+    (call lp3 simbranch n st sp lam mu rho)
+    (weight (+ lp1 (+ lp2 lp3)))
+    (resample)
+    (if (>= (at left node) 0)
+        ((call a simtree (at left node) node lam mu rho) (call b simtree (at right node) node lam mu rho))
+        ())
+    (return 0))
+  (def lnfact (i k acc)
+    (if (> i k) ((return acc)) ((call r lnfact (+ i 1) k (+ acc (log i))) (return r))))
+  (def main ()
+    {prior}
+    (call lf lnfact 2 {tips} 0)
+    (weight (- (* {tips - 1} (log 2)) lf))
+    (resample)
+    (call a simtree (at left 0) 0 lam mu {_num(rho)})
+    (call b simtree (at right 0) 0 lam mu {_num(rho)})
+    (return lam)))"""

@@ -52,13 +52,14 @@ def PO(oracle):
 PROGRAMS = {
     "geometric": lambda: I.geometric_program(0.5, 1.2),
     "lgssm_tail": lambda: I.lgssm_program(I.lgssm_data(16, 2000), tail=True),
+    "crbd": lambda: I.crbd_program(I.yule_tree(20, 1000)),
     "lgssm": lambda: I.lgssm_program(I.lgssm_data(16, 2000)),
     "hmm": lambda: I.hmm_program(I.hmm_observations(14, 7)),
     "branching": lambda: I.branching_program(I.branching_observations(7, 8)),
 }
 
 
-def program_model(smc, ctx, txt, stack_words=256, ess=0.0):
+def program_model(smc, ctx, txt, stack_words=512, ess=0.0):
     img = ppl.compile_program(txt, stack_words)
     return smc.Model(ctx, {"kind": "program", "precision": 64, "program": img, "ess_threshold": ess}), img
 
@@ -99,7 +100,7 @@ def lockstep(smc, run, ref, oracle, label):
 @pytest.mark.parametrize("name", list(PROGRAMS))
 @pytest.mark.parametrize("n", [1, 1000, 4099])
 def test_program_matches_oracle(smc, ctx, oracle, PO, name, n):
-    if name in ("lgssm", "lgssm_tail", "branching") and n == 4099:
+    if name in ("lgssm", "lgssm_tail", "branching", "crbd") and n == 4099:
         n = 2051  # the pure-Python oracle sets the size
     txt = PROGRAMS[name]()
     model, _ = program_model(smc, ctx, txt)

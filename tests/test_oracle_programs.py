@@ -159,3 +159,25 @@ def test_faults_stop_the_particle(oracle, PO):
     r.step()
     assert np.isneginf(r.lw).all()
     assert r.resample() == oracle.DEGENERATE
+
+
+SMALL_TREE = ((((0.0, 0.0, 0.21), 0.0, 0.55), ((0.0, 0.0, 0.33), 0.0, 0.62), 1.0))
+
+
+def test_crbd_program_unbiased_for_closed_form(oracle, PO):
+    """The Appendix CRBD model compiled from source (fixed rates): the
+    estimate is unbiased for the closed-form tree likelihood, as for the
+    built-in model."""
+    import analytic as A
+    tree = I.tree_from_newick_like(SMALL_TREE)
+    lam, mu = 1.5, 0.8
+    L = math.exp(A.crbd_log_lik(tree, lam, mu))
+    txt = I.crbd_program(tree, fixed=(lam, mu))
+    ratios = []
+    for s in range(3000):
+        r = PO.ProgramRun(txt, 4, s)
+        st = r.run_to_end()
+        ratios.append(math.exp(r.log_z) / L if st == oracle.FINISHED else 0.0)
+    ratios = np.array(ratios)
+    se = ratios.std(ddof=1) / math.sqrt(len(ratios))
+    assert abs(ratios.mean() - 1.0) <= 4 * se, (ratios.mean(), se)

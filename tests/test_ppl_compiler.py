@@ -393,6 +393,7 @@ PROGRAMS = {
     "geometric": (lambda: I.geometric_program(0.5, 1.2), 64),
     "lgssm_tail": (lambda: I.lgssm_program(I.lgssm_data(12, 2000), tail=True), 96),
     "returns_in_branches": (lambda: SIGN_PROGRAM, 64),
+    "crbd": (lambda: I.crbd_program(I.yule_tree(8, 7)), 48),
     "lgssm": (lambda: I.lgssm_program(I.lgssm_data(12, 2000)), 96),
     "hmm": (lambda: I.hmm_program(I.hmm_observations(10, 7)), 64),
     "branching": (lambda: I.branching_program(I.branching_observations(6, 8)), 96),
