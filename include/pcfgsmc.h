@@ -299,7 +299,9 @@ smc_status smc_reset(smc_run* run, uint64_t seed);
  * the ESS rule kept the weights), or
  * SMC_READ_FIELD0 + k for state field k in the model's field order (real fields
  * in the storage precision, then int32 fields, then the ClaDS rate stack as
- * [particle][level] with smc_run_stats().stack_depth levels). State is returned
+ * [particle][level] with smc_run_stats().stack_depth levels; for a compiled
+ * program: int32 stack pointer, then the stack as [particle][word] of
+ * stack_words FP64 words, of which the first sp are live). State is returned
  * as Algorithm 1 holds it: after smc_resample, already gathered by ancestor.
  * bytes must be at least the size of the array. */
 enum { SMC_READ_BLK = 0, SMC_READ_LW = 1, SMC_READ_ANC = 2, SMC_READ_FIELD0 = 16 };
