@@ -340,6 +340,39 @@ def crbd_program_point(smc, ctx, I, tree, n: int = 1 << 20, runs: int = 2):
             "log_z": zs, "kernel_ms_per_run": {k: round(v[0], 3) for k, v in kt.items()}}
 
 
+def seir_program_point(smc, ctx, I, n: int = 1 << 16, days: int = 100, runs: int = 2):
+    """The vector-borne disease model compiled from source, beside the built-in
+    SEIR block table at FP64 state on the same data and seed (same bits)."""
+    import torch
+    from paper_2112_00364_amd import ppl
+    y = I.seir_data(days, 6000)
+    img = ppl.compile_program(I.seir_program(y), stack_words=2800)
+    out = {"workload": f"seir_program_synthetic{days}d_n{n}", "particles": n, "days": days, "runs": runs,
+           "blocks": img.n_blocks, "frame_words": dict(img.frames)}
+    zs = {}
+    for key, spec in (("program", {"kind": "program", "precision": 64, "program": img}),
+                      ("builtin", I.seir_spec(y, 64))):
+        model = smc.Model(ctx, spec)
+        run = smc.Run(model, n, 61)
+        run.run_to_end()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(ctx.stream)
+        for i in range(runs):
+            run.reset(62 + i)
+            run.run_to_end()
+        end.record(ctx.stream)
+        torch.cuda.synchronize()
+        out[f"{key}_ms_per_run"] = start.elapsed_time(end) / runs
+        zs[key] = run.stats()["log_z"]
+        run.close()
+        model.close()
+    out["same_log_z"] = zs["program"] == zs["builtin"]
+    out["log_z"] = zs["program"]
+    return out
+
+
 def bucketing_point(smc, ctx, I, n: int = 1 << 20, T: int = 12, runs: int = 2):
     """Block bucketing on a program whose particles resume at two different
     blocks every round (regime_program: resampling inside the branch of a
@@ -583,6 +616,9 @@ def main():
     if not args.no_program:
         print("compiled-program point", file=sys.stderr, flush=True)
         out["program"] = program_point(smc, ctx, I, cpu=not args.no_cpu_baseline, tail=not args.no_tail_call)
+    if not args.no_seir and not args.no_program:
+        print("compiled SEIR point", file=sys.stderr, flush=True)
+        out["seir_program"] = seir_program_point(smc, ctx, I)
     if not args.no_crbd_program:
         print("compiled CRBD point", file=sys.stderr, flush=True)
         out["crbd_program"] = crbd_program_point(smc, ctx, I, tree)

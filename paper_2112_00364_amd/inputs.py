@@ -465,3 +465,58 @@ def crbd_program(tree, rho=1.0, scale_lambda=1.0, scale_mu=0.5, fixed=None) -> s
     (call a simtree (at left 0) 0 lam mu {_num(rho)})
     (call b simtree (at right 0) 0 lam mu {_num(rho)})
     (return lam)))"""
+
+
+def seir_program(y, n=SEIR_HUMANS) -> str:
+    """The vector-borne disease model of the Appendix listing as a program for
+    the compiler, with the built-in SEIR model's draw order and arithmetic
+    (priors, initial counts, then one day per round: human transitions, then
+    mosquito transitions, survival and births, and the reported-case
+    observation), so at FP64 the two give the same bits. Each day resamples
+    first, so the day's new counts pass straight into the next day's call."""
+    ys = " ".join(_num(v) for v in y)
+    return f"""(program
+  (data y {ys})
+  (def day (t hS hE hI hR mS mE mI mR z hl hd hg ml md rho)
+    (resample)
+    (let hN (+ (+ (+ hS hE) hI) hR))
+    (sample hTau binomial hS (- 1 (exp (neg (/ mI hN)))))
+    (sample hDE binomial hTau hl)
+    (sample hDI binomial hE hd)
+    (sample hDR binomial hI hg)
+    (sample mTau binomial mS (- 1 (exp (neg (/ hI hN)))))
+    (let mN (+ (+ (+ mS mE) mI) mR))
+    (sample mDE binomial mTau ml)
+    (sample mDI binomial mE md)
+    (sample mDR binomial mI 0)
+    (sample mS2 binomial (- mS mDE) (/ 6.0 7.0))
+    (sample mE2 binomial (- (+ mE mDE) mDI) (/ 6.0 7.0))
+    (sample mI2 binomial (- (+ mI mDI) mDR) (/ 6.0 7.0))
+    (sample mR2 binomial (+ mR mDR) (/ 6.0 7.0))
+    (sample mDS binomial mN (/ 1.0 7.0))
+    (let z2 (+ z hDI))
+    (if (!= (at y t) -1) ((observe binomial z2 rho (at y t)) (let z2 0)) ())
+    (if (< (+ t 1) (len y))
+        ((call u day (+ t 1) (- hS hDE) (- (+ hE hDE) hDI) (- (+ hI hDI) hDR) (+ hR hDR)
+               (+ mS2 mDS) mE2 mI2 mR2 z2 hl hd hg ml md rho))
+        ())
+    (return 0))
+  (def main ()
+    (sample hl beta 1.0 1.0)
+    (sample hd beta (+ 1.0 (/ 2.0 4.4)) (- 3.0 (/ 2.0 4.4)))
+    (sample hg beta (+ 1.0 (/ 2.0 4.5)) (- 3.0 (/ 2.0 4.5)))
+    (sample ml beta 1.0 1.0)
+    (sample md beta (+ 1.0 (/ 2.0 6.5)) (- 3.0 (/ 2.0 6.5)))
+    (sample rho beta 1.0 1.0)
+    (sample k poisson 5.0)
+    (let hI (+ 1 k))
+    (sample hE poisson 5.0)
+    (sample u uniform 0.0 (+ (- (- {n} hI) hE) 1))
+    (let hR (floor u))
+    (sample v uniform -1.0 2.0)
+    (let mS (floor (* {n} (exp (* v (log 10))))))
+    (let hS (- (- (- {n} hE) hI) hR))
+    (let z hI)
+    (if (!= (at y 0) -1) ((observe binomial z rho (at y 0)) (let z 0)) ())
+    (if (> (len y) 1) ((call w day 1 hS hE hI hR mS 0 0 0 z hl hd hg ml md rho)) ())
+    (return 0)))"""

@@ -174,6 +174,29 @@ def test_tail_recursive_program_equals_builtin_with_constant_stack(smc, ctx):
     assert a.log_z() == b.log_z()
 
 
+def test_seir_program_equals_builtin(smc, ctx):
+    """The vector-borne disease model written as a program against the
+    built-in SEIR block table (FP64 state), all 100 days, 2^16 particles."""
+    y = I.seir_data(100, 6000)
+    model, img = program_model(smc, ctx, I.seir_program(y), stack_words=2800)
+    builtin = smc.Model(ctx, I.seir_spec(y, 64))
+    n = 1 << 16
+    a = smc.Run(model, n, 61)
+    b = smc.Run(builtin, n, 61)
+    for r in range(100):
+        a.step()
+        b.step()
+        if r % 33 == 0 or r == 99:
+            say("seir program vs built-in round", r)
+            assert np.array_equal(bits(a.lw()), bits(b.lw()))
+        a.resample()
+        b.resample()
+        if a.done()[0]:
+            break
+    assert a.done() == b.done() == (True, smc.FINISHED)
+    assert a.log_z() == b.log_z()
+
+
 def test_stack_contents_match_bytecode_simulation(smc, ctx, oracle):
     import bytecode_sim as BS
     txt = PROGRAMS["branching"]()

@@ -181,3 +181,22 @@ def test_crbd_program_unbiased_for_closed_form(oracle, PO):
     ratios = np.array(ratios)
     se = ratios.std(ddof=1) / math.sqrt(len(ratios))
     assert abs(ratios.mean() - 1.0) <= 4 * se, (ratios.mean(), se)
+
+
+@pytest.mark.parametrize("seed", [1, 4])
+def test_seir_program_is_the_builtin_model(oracle, PO, seed):
+    """The Appendix vector-borne disease model written as a program equals the
+    C oracle's built-in SEIR model (FP64 state) bit for bit."""
+    y = I.seir_data(10, 6000)
+    a = PO.ProgramRun(I.seir_program(y), 96, seed)
+    b = oracle.Run(I.seir_spec(y, 64), 96, seed)
+    while True:
+        a.step()
+        b.step()
+        assert np.array_equal(a.lw.view(np.uint64), b.lw().view(np.uint64))
+        sa, sb = a.resample(), b.resample()
+        assert sa == sb
+        if sa != oracle.OK:
+            break
+        assert np.array_equal(a.anc, b.anc())
+    assert a.log_z == b.log_z

@@ -394,6 +394,7 @@ PROGRAMS = {
     "lgssm_tail": (lambda: I.lgssm_program(I.lgssm_data(12, 2000), tail=True), 96),
     "returns_in_branches": (lambda: SIGN_PROGRAM, 64),
     "crbd": (lambda: I.crbd_program(I.yule_tree(8, 7)), 48),
+    "seir": (lambda: I.seir_program(I.seir_data(6, 6000)), 48),
     "lgssm": (lambda: I.lgssm_program(I.lgssm_data(12, 2000)), 96),
     "hmm": (lambda: I.hmm_program(I.hmm_observations(10, 7)), 64),
     "branching": (lambda: I.branching_program(I.branching_observations(6, 8)), 96),
