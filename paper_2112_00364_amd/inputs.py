@@ -473,7 +473,8 @@ def seir_program(y, n=SEIR_HUMANS) -> str:
     (priors, initial counts, then one day per round: human transitions, then
     mosquito transitions, survival and births, and the reported-case
     observation), so at FP64 the two give the same bits. Each day resamples
-    first, so the day's new counts pass straight into the next day's call."""
+    first, so the day's new counts pass straight into the next day's call,
+    a self tail call: the stack stays at main's frame plus one day frame."""
     ys = " ".join(_num(v) for v in y)
     return f"""(program
   (data y {ys})
@@ -498,9 +499,9 @@ def seir_program(y, n=SEIR_HUMANS) -> str:
     (if (!= (at y t) -1) ((observe binomial z2 rho (at y t)) (let z2 0)) ())
     (if (< (+ t 1) (len y))
         ((call u day (+ t 1) (- hS hDE) (- (+ hE hDE) hDI) (- (+ hI hDI) hDR) (+ hR hDR)
-               (+ mS2 mDS) mE2 mI2 mR2 z2 hl hd hg ml md rho))
-        ())
-    (return 0))
+               (+ mS2 mDS) mE2 mI2 mR2 z2 hl hd hg ml md rho)
+         (return u))
+        ((return 0))))
   (def main ()
     (sample hl beta 1.0 1.0)
     (sample hd beta (+ 1.0 (/ 2.0 4.4)) (- 3.0 (/ 2.0 4.4)))

@@ -267,7 +267,9 @@ def _end_paths(stmts, on_return, on_fallthrough):
     return stmts + on_fallthrough()
 
 
-MAX_TAIL_ARGS = N_REGS - REG_LOCALS  # arguments are held in registers while the frame is rewritten
+# A self tail call's arguments are held in registers while the parameters are
+# rewritten; beyond this many they go through temporary frame slots instead.
+MAX_TAIL_ARGS = N_REGS - REG_LOCALS
 
 
 def _tail_calls(f, params, stmts):
@@ -275,7 +277,7 @@ def _tail_calls(f, params, stmts):
     list -> `(tailcall f ...)` (self-calls only)."""
     if len(stmts) >= 2 and stmts[-1][0] == "return" and stmts[-2][0] == "call":
         c = stmts[-2]
-        if c[2] == f and stmts[-1][1] == ("var", c[1]) and len(c[3]) <= MAX_TAIL_ARGS:
+        if c[2] == f and stmts[-1][1] == ("var", c[1]):
             return stmts[:-2] + [("tailcall", f, c[3])]
     if stmts and stmts[-1][0] == "if":
         s = stmts[-1]
@@ -667,10 +669,18 @@ class _Gen:
                     if it[1] != RETURN:
                         raise CompileError("internal: tail call not in tail position")
                     params = self.src.functions[f].params
-                    for i, e in enumerate(s[2]):
-                        self.expr(e, i, f, out)
-                    for i, p in enumerate(params):
-                        out.append(["STF", i, 0, 0, self.slots[f][p]])
+                    if len(s[2]) <= min(MAX_TAIL_ARGS, self.limit):
+                        for i, e in enumerate(s[2]):
+                            self.expr(e, i, f, out)
+                        for i, p in enumerate(params):
+                            out.append(["STF", i, 0, 0, self.slots[f][p]])
+                    else:  # through the frame's tail temporaries
+                        for i, e in enumerate(s[2]):
+                            self.expr(e, 0, f, out)
+                            out.append(["STF", 0, 0, 0, self.slots[f][f"$tail{i}"]])
+                        for i, p in enumerate(params):
+                            out.append(["LDF", 0, 0, 0, self.slots[f][f"$tail{i}"]])
+                            out.append(["STF", 0, 0, 0, self.slots[f][p]])
                     out.append(["GOTO", 0, 0, 0, self.entries[f]])
                     continue
                 if it[1] == RETURN:
@@ -751,6 +761,8 @@ def compile_program(text: str, stack_words: int = 256) -> ProgramImage:
             block_regs[idx] = {v: N_REGS - 1 - i for i, v in enumerate(mine)}
             in_regs.update(mine)
         names = params + [v for v in assigned if v not in in_regs]
+        if any(s[0] == "tailcall" for s in _walk(bodies[f])) and len(params) > MAX_TAIL_ARGS:
+            names += [f"$tail{i}" for i in range(len(params))]  # staging for a long tail call
         slots[f] = {v: 2 + i for i, v in enumerate(names)}
         frames[f] = 2 + len(names)
     # final numbering: 0 = start block, then each function's blocks, entry first

@@ -260,7 +260,7 @@ def test_self_tail_calls_reuse_the_frame(oracle):
 
 def test_program_too_deep_for_registers():
     e = "1"
-    for _ in range(20):
+    for _ in range(40):
         e = f"(+ 1 {e})"
     with pytest.raises(ppl.CompileError, match="registers"):
         ppl.compile_program(f"(program (def main () (let a (+ {e} {e}))))")
@@ -312,7 +312,7 @@ def _mutations(img):
     out = []
     i = where("LDF")[0]
     out.append(("opcode", with_code(i, _enc("FAULT") + 200 - ppl.OPS["FAULT"])))
-    out.append(("register", with_code(i, _enc("LDF", x=16, imm=2))))
+    out.append(("register", with_code(i, _enc("LDF", x=ppl.N_REGS, imm=2))))
     out.append(("frame offset", with_code(i, _enc("LDF", imm=200))))
     c = where("CONST")[0]
     out.append(("constant", with_code(c, _enc("CONST", imm=10 ** 6))))
