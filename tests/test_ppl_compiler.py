@@ -258,6 +258,28 @@ def test_self_tail_calls_reuse_the_frame(oracle):
     assert "CALLFRAME" not in {op for op, *_ in step_code}
 
 
+def test_long_self_tail_call_stages_arguments_in_the_frame(oracle):
+    """The SEIR day recursion passes 16 arguments, more than the register
+    budget: they are staged through frame temporaries and the stack still
+    stays at main's frame plus one day frame, with the built-in model's bits."""
+    import bytecode_sim as BS
+    y = I.seir_data(15, 6000)
+    img = ppl.compile_program(I.seir_program(y), 128)
+    assert img.frames["day"] >= 2 + 16 + 16
+    sim = BS.SimRun(img, 48, 3)
+    ref = oracle.Run(I.seir_spec(y, 64), 48, 3)
+    depth = 0
+    while sim.status == oracle.OK:
+        sim.step()
+        ref.step()
+        assert np.array_equal(sim.lw(), ref.lw())
+        depth = max(depth, max(q[1] for q in sim.p))
+        sim.resample()
+        ref.resample()
+    assert sim.log_z == ref.log_z
+    assert depth == img.frames["main"] + img.frames["day"]
+
+
 def test_program_too_deep_for_registers():
     e = "1"
     for _ in range(40):
