@@ -347,7 +347,10 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
 smc_status smc_batch_create(smc_ctx* ctx, smc_batch** out);
 /* Add a run (Algorithm 1 step 1 for it); *slot receives its index. */
 smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n_particles, uint64_t seed, int32_t* slot);
-/* Advance every live run by up to `rounds` rounds (step + resample each). */
+/* Advance every live run by up to `rounds` rounds (step + resample each).
+ * From the second tick with the same runs and round count on, the tick's
+ * launch sequence is captured once into a HIP graph and replayed; adding or
+ * retiring a run drops the graph. Results are the same either way. */
 smc_status smc_batch_tick(smc_batch* b, int32_t rounds);
 /* Synchronises. done[i] = 1 for finished (or failed) slots; log_z[i] their
  * estimates; status[i] their status. Arrays are host, length = slots. */

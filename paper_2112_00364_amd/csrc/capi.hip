@@ -1035,6 +1035,15 @@ struct smc_batch {
     bool any_unfused = false;
     std::vector<std::vector<TileRef>> group_tiles_h;
     std::vector<TileRef> red_tiles_h;
+    // A tick of an unchanged batch is a fixed launch sequence: from the second
+    // such tick on it is captured once and replayed.
+    hipGraphExec_t graph = nullptr;
+    int32_t graph_rounds = 0;
+    uint32_t same_ticks = 0;
+    ~smc_batch()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+    }
 };
 
 namespace {
@@ -1043,6 +1052,11 @@ smc_status rebuild_tables(smc_batch* b)
 {
     hipStream_t st = b->ctx->stream;
     HIP_TRY(hipStreamSynchronize(st));  // old tables may still be in use
+    if (b->graph) {  // it launches over the old tables
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    b->same_ticks = 0;
     b->tables.release_all();
     b->groups.clear();
     b->runs_h.clear();
@@ -1134,12 +1148,47 @@ smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
     }
     if (b->runs_h.empty()) return SMC_OK;
     hipStream_t st = b->ctx->stream;
-    for (int32_t k = 0; k < rounds; ++k) {
-        for (const auto& g : b->groups) HIP_TRY(launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, st));
+    auto enqueue = [&](hipStream_t s) -> hipError_t {
         const uint32_t n_runs = (uint32_t)b->runs_h.size();
-        HIP_TRY(launch_reduce(b->runs, b->red_tiles, b->n_red, n_runs, b->any_unfused, st));
-        HIP_TRY(launch_scan_anc(b->runs, b->red_tiles, b->n_red, st));
+        for (int32_t k = 0; k < rounds; ++k) {
+            for (const auto& g : b->groups) {
+                const hipError_t e = launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, s);
+                if (e != hipSuccess) return e;
+            }
+            hipError_t e = launch_reduce(b->runs, b->red_tiles, b->n_red, n_runs, b->any_unfused, s);
+            if (e == hipSuccess) e = launch_scan_anc(b->runs, b->red_tiles, b->n_red, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    if (b->graph && b->graph_rounds != rounds) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
     }
+    if (!b->graph && b->same_ticks >= 1 && rounds > 0) {
+        // Capture on a private stream (capture needs a non-legacy stream); if
+        // it fails the tick simply runs eagerly.
+        hipStream_t cap = nullptr;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess) {
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) e = enqueue(cap);
+            const hipError_t e2 = hipStreamEndCapture(cap, &g);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) b->graph = nullptr;
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cap);
+            (void)hipGetLastError();
+            if (b->graph) b->graph_rounds = rounds;
+        }
+    }
+    if (b->graph) {
+        HIP_TRY(hipGraphLaunch(b->graph, st));
+    } else {
+        HIP_TRY(enqueue(st));
+    }
+    b->same_ticks += 1;
     for (smc_run* r : b->slots)
         if (r) r->rounds_issued += (uint32_t)rounds;
     return SMC_OK;

@@ -70,3 +70,37 @@ def test_batch_retire_and_reuse_slots(ctx, oracle):
     assert abs(lz[s1] - ref.log_z) <= 1e-9 * abs(ref.log_z)
     b.close()
     m.close()
+
+
+def test_batch_tick_graph_replays_match_runs_alone(ctx):
+    """From the second tick of an unchanged batch on, the tick is a captured
+    graph replayed; with polls (synchronisation, host reads) between replays,
+    every run still ends exactly as alone. Adding a run drops the graph and the
+    next ticks capture again."""
+    from paper_2112_00364_amd import smc
+    models = [smc.Model(ctx, I.crbd_spec(I.yule_tree(24, 31), precision=64)),
+              smc.Model(ctx, I.lgssm_spec(I.lgssm_data(40, 5), 32)),
+              smc.Model(ctx, I.geometric_spec(True, 0.5, 1.2))]
+    sizes = [3000, 2048, 1500]
+    alone = []
+    for m, n in zip(models, sizes):
+        r = smc.Run(m, n, 12)
+        r.run_to_end()
+        alone.append(r.log_z())
+        r.close()
+    b = smc.Batch(ctx)
+    slots = [b.add(m, n, 12) for m, n in zip(models[:2], sizes[:2])]
+    ticks = 0
+    for _ in range(200):
+        b.tick(3)
+        ticks += 1
+        done, lz, st, _ = b.poll()
+        if ticks == 4:  # composition changes mid-way: the graph is dropped and captured again
+            slots.append(b.add(models[2], sizes[2], 12))
+        if len(slots) == 3 and done[:3].all():
+            break
+    assert ticks > 6
+    done, lz, st, _ = b.poll()
+    for s, want in zip(slots, alone):
+        assert lz[s] == want, (s, lz[s], want)
+    b.close()
