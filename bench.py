@@ -408,7 +408,7 @@ def bucketing_point(smc, ctx, I, n: int = 1 << 20, T: int = 12, runs: int = 2):
         run.profile(False)
         out[f"kernel_ms_per_run_bucketing_{key}"] = {k: round(v[0], 3) for k, v in kt.items()}
     out["same_log_z"] = zs["on"] == zs["off"]
-    out["autotuner"] = autotune.choose_bucketing(run, 96, rounds=4, repeats=2)
+    out["autotuner"] = autotune.choose_launch(run, 96, rounds=4, repeats=2)
     run.close()
     model.close()
     return out

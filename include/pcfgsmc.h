@@ -275,6 +275,11 @@ smc_status smc_run_to_end(smc_run* run);
 smc_status smc_snapshot(smc_run* run, void* host_dst, size_t* bytes);
 smc_status smc_restore(smc_run* run, const void* host_src, size_t bytes);
 
+/* Lanes per work-group of a single run's propagation: 128 or 256 (the
+ * default depends on the model kind; batches keep it). The results do not
+ * depend on it. Synchronises; a captured graph of the run is dropped. */
+smc_status smc_set_workgroup(smc_run* run, int32_t lanes);
+
 /* Block bucketing. Particles may sit at different blocks of the PCFG at the
  * same time (Sec. 3.2), and lanes of one wavefront running different blocks
  * take turns. enable = 1: before every smc_step the

@@ -289,6 +289,7 @@ size_t real_bytes(const smc_model* m) { return m->precision == 32 ? 4 : 8; }
 // Allocate and initialise a run's device state (Alg. 1 step 1).
 void set_prop_tiles(RunDev& h, int lanes)
 {
+    h.lanes = (uint32_t)lanes;
     h.prop_tiles = (uint32_t)((h.n + lanes - 1) / lanes);
     h.fused = h.red_tiles <= kMaxFusedRedTiles ? 1u : 0u;
 }
@@ -783,6 +784,22 @@ smc_status smc_restore(smc_run* r, const void* host_src, size_t bytes)
     r->rounds_issued = hd.rounds_issued;
     r->expect_step = hd.expect_step != 0;
     r->known_status = hd.known_status;
+    return SMC_OK;
+}
+
+smc_status smc_set_workgroup(smc_run* r, int32_t lanes)
+{
+    if (!r) return fail(SMC_ERR_INVALID, "NULL run");
+    if (lanes != 128 && lanes != 256) return fail(SMC_ERR_INVALID, "lanes must be 128 or 256");
+    if (r->host.lanes == (uint32_t)lanes) return SMC_OK;
+    set_prop_tiles(r->host, lanes);
+    r->n_prop = r->host.prop_tiles;
+    HIP_TRY(hipMemcpyAsync(r->dev, &r->host, sizeof(RunDev), hipMemcpyHostToDevice, r->ctx->stream));
+    HIP_TRY(hipStreamSynchronize(r->ctx->stream));
+    if (r->graph) {  // the captured launches have the old shape
+        (void)hipGraphExecDestroy(r->graph);
+        r->graph = nullptr;
+    }
     return SMC_OK;
 }
 

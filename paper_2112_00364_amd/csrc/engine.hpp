@@ -36,10 +36,10 @@ struct ParticleBuf {
 struct RunDev {
     uint32_t n;
     uint32_t red_tiles;            // reduction / scan tiles of kTileRed particles
-    uint32_t prop_tiles;           // propagation tiles of prop_threads(kind) particles
+    uint32_t prop_tiles;           // propagation tiles of `lanes` particles
     uint32_t fused;                // 1: the reduction and scan fold the partials themselves
     uint32_t ess_t;                // ESS threshold numerator over 2^16 (0: resample every round)
-    uint32_t pad_;
+    uint32_t lanes;                // lanes per propagation work-group (128 or 256; smc_set_workgroup)
     const ModelDev* model;
     RunCtl* ctl;
     ParticleBuf buf[2];            // buf[r & 1] is written by the propagation of round r
@@ -59,9 +59,10 @@ struct RunDev {
     uint32_t* bucket_total;        // [kBuckets]
 };
 
-// Lanes (= particles) per propagation work-group, by model kind: 128 for the
-// tree models and the small ones (finer scheduling of divergent blocks),
-// 256 for the SEIR model (measured faster). The resampling-only entry point
+// Default lanes (= particles) per propagation work-group, by model kind: 128
+// for the tree models and the small ones (finer scheduling of divergent
+// blocks), 256 for the SEIR model (measured faster). A single run can switch
+// to the other size (smc_set_workgroup); batches use the default. The resampling-only entry point
 // takes its maxima over tiles of kMaxkeyThreads.
 __host__ __device__ constexpr int prop_threads(int kind) { return kind == 4 ? 256 : 128; }
 constexpr int kMaxkeyThreads = 256;

@@ -685,10 +685,9 @@ __device__ __forceinline__ void program_body(const RunDev& R, uint32_t tile)
 // needs more is recomputed, in the same work-group, one lane of its wavefront
 // at a time with a kMaxDepthCap-frame stack in LDS; its random stream is
 // counter-based, so the recomputation draws the same words.
-template <int Kind, class Real>
+template <int Kind, class Real, int kThreads>
 __device__ __forceinline__ void builtin_body(const RunDev& R, uint32_t tile)
 {
-    constexpr int kThreads = prop_threads(Kind);
     const uint32_t j = lane_slot(R, tile * kThreads + threadIdx.x);
     const bool valid = j < R.n;
     RunCtl* ctl = R.ctl;
@@ -735,19 +734,19 @@ __device__ __forceinline__ void builtin_body(const RunDev& R, uint32_t tile)
     publish_tile_partial<kThreads>(R, tile, p, &s_arrived);
 }
 
-template <int Kind, class Real>
+template <int Kind, class Real, int kThreads>
 __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
 {
-    if constexpr (Kind == 6) program_body<prop_threads(6)>(R, tile);
-    else builtin_body<Kind, Real>(R, tile);
+    if constexpr (Kind == 6) program_body<kThreads>(R, tile);
+    else builtin_body<Kind, Real, kThreads>(R, tile);
 }
 
 // Entry points: one run (its record is a kernel argument, tile = work-group)
 // or a batch (work-group -> (run, tile) table).
-template <int Kind, class Real>
-__global__ __launch_bounds__(prop_threads(Kind)) void k_propagate_one(const RunDev R)
+template <int Kind, class Real, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_propagate_one(const RunDev R)
 {
-    propagate_body<Kind, Real>(R, blockIdx.x);
+    propagate_body<Kind, Real, kThreads>(R, blockIdx.x);
 }
 
 template <int Kind, class Real>
@@ -755,7 +754,7 @@ __global__ __launch_bounds__(prop_threads(Kind)) void k_propagate(const RunDev* 
                                                              const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
-    propagate_body<Kind, Real>(runs[tr.run], tr.tile);
+    propagate_body<Kind, Real, prop_threads(Kind)>(runs[tr.run], tr.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -1429,22 +1428,27 @@ hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const T
     return hipGetLastError();
 }
 
+template <int Kind, class Real>
+static hipError_t launch_one_sized(const RunDev& run, hipStream_t st)
+{
+    const dim3 g(run.prop_tiles);
+    if (run.lanes == 256) hipLaunchKernelGGL((k_propagate_one<Kind, Real, 256>), g, dim3(256), 0, st, run);
+    else hipLaunchKernelGGL((k_propagate_one<Kind, Real, 128>), g, dim3(128), 0, st, run);
+    return hipGetLastError();
+}
+
 hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipStream_t st)
 {
-    dim3 g(run.prop_tiles), b(prop_threads(kind));
-    if (kind == 0) hipLaunchKernelGGL((k_propagate_one<0, double>), g, b, 0, st, run);
-    else if (kind == 1 && precision == 32) hipLaunchKernelGGL((k_propagate_one<1, float>), g, b, 0, st, run);
-    else if (kind == 1) hipLaunchKernelGGL((k_propagate_one<1, double>), g, b, 0, st, run);
-    else if (kind == 2 && precision == 32) hipLaunchKernelGGL((k_propagate_one<2, float>), g, b, 0, st, run);
-    else if (kind == 2) hipLaunchKernelGGL((k_propagate_one<2, double>), g, b, 0, st, run);
-    else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate_one<3, float>), g, b, 0, st, run);
-    else if (kind == 3) hipLaunchKernelGGL((k_propagate_one<3, double>), g, b, 0, st, run);
-    else if (kind == 4 && precision == 32) hipLaunchKernelGGL((k_propagate_one<4, float>), g, b, 0, st, run);
-    else if (kind == 4) hipLaunchKernelGGL((k_propagate_one<4, double>), g, b, 0, st, run);
-    else if (kind == 6) hipLaunchKernelGGL((k_propagate_one<6, double>), g, b, 0, st, run);
-    else if (precision == 32) hipLaunchKernelGGL((k_propagate_one<5, float>), g, b, 0, st, run);
-    else hipLaunchKernelGGL((k_propagate_one<5, double>), g, b, 0, st, run);
-    return hipGetLastError();
+    const bool f32 = precision == 32;
+    switch (kind) {
+    case 0: return launch_one_sized<0, double>(run, st);
+    case 1: return f32 ? launch_one_sized<1, float>(run, st) : launch_one_sized<1, double>(run, st);
+    case 2: return f32 ? launch_one_sized<2, float>(run, st) : launch_one_sized<2, double>(run, st);
+    case 3: return f32 ? launch_one_sized<3, float>(run, st) : launch_one_sized<3, double>(run, st);
+    case 4: return f32 ? launch_one_sized<4, float>(run, st) : launch_one_sized<4, double>(run, st);
+    case 6: return launch_one_sized<6, double>(run, st);
+    default: return f32 ? launch_one_sized<5, float>(run, st) : launch_one_sized<5, double>(run, st);
+    }
 }
 
 hipError_t launch_bucket(const RunDev& run, hipStream_t st)

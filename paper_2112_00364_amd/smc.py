@@ -137,6 +137,7 @@ def lib():
         "smc_run_to_end": [vp],
         "smc_reset": [vp, u64],
         "smc_set_bucketing": [vp, i32],
+        "smc_set_workgroup": [vp, i32],
         "smc_snapshot": [vp, vp, C.POINTER(C.c_size_t)],
         "smc_restore": [vp, vp, C.c_size_t],
         "smc_read": [vp, i32, vp, C.c_size_t],
@@ -331,6 +332,10 @@ class Run:
         """Load a snapshot of a run of the same model and size (resume)."""
         buf = C.create_string_buffer(snap, len(snap))
         _check(lib().smc_restore(self._h, C.cast(buf, C.c_void_p), len(snap)))
+
+    def set_workgroup(self, lanes: int):
+        """Lanes per propagation work-group, 128 or 256 (results unchanged)."""
+        _check(lib().smc_set_workgroup(self._h, int(lanes)))
 
     def set_bucketing(self, enable: bool = True):
         """Sort particle slots by resume block before each propagation (results unchanged)."""

@@ -136,3 +136,45 @@ def test_autotuner_keeps_results(smc, ctx):
     assert set(choice) == {"bucketing", "ms_off", "ms_on", "rounds"}
     assert run.run_to_end() == smc.FINISHED
     assert run.log_z() == ref.log_z()
+
+
+@pytest.mark.parametrize("name", ["crbd", "seir", "regime"])
+def test_workgroup_size_changes_no_result(smc, ctx, name):
+    """smc_set_workgroup changes the propagation's lanes per work-group (128 or
+    256), never the results."""
+    if name == "seir":
+        model = smc.Model(ctx, I.seir_spec(I.seir_data(20, 6000), 32))
+    elif name == "crbd":
+        model = MODELS["crbd"](smc, ctx)
+    else:
+        model = MODELS["regime"](smc, ctx)
+    n = 4099
+    zs, lws = [], []
+    for lanes in (128, 256):
+        run = smc.Run(model, n, 23)
+        run.set_workgroup(lanes)
+        for _ in range(3):
+            run.step()
+            run.resample()
+        lws.append(run.lw())
+        run.run_to_end()
+        zs.append(run.log_z())
+        run.close()
+    assert np.array_equal(bits(lws[0]), bits(lws[1]))
+    assert zs[0] == zs[1]
+    with pytest.raises(smc.SMCError):
+        smc.Run(model, 64, 1).set_workgroup(96)
+
+
+def test_launch_autotuner_keeps_results(smc, ctx):
+    from paper_2112_00364_amd import autotune
+    model = program(smc, ctx, I.regime_program(I.branching_observations(8, 9), draws=6))
+    n = 1 << 15
+    ref = smc.Run(model, n, 21)
+    ref.run_to_end()
+    run = smc.Run(model, n, 21)
+    choice = autotune.choose_launch(run, 21, rounds=3, repeats=1)
+    say("launch autotuner", choice)
+    assert choice["lanes"] in (128, 256) and len(choice["ms"]) == 4
+    assert run.run_to_end() == smc.FINISHED
+    assert run.log_z() == ref.log_z()
