@@ -27,7 +27,7 @@ READ_BLK, READ_LW, READ_ANC, READ_FIELD0 = 0, 1, 2, 16
 
 def build() -> str:
     """Compile the oracle with gcc (always recompiles)."""
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.{os.getpid()}.tmp"  # per process: concurrent builds do not collide
     subprocess.run(["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"], check=True)
     os.replace(tmp, LIB)
     return LIB

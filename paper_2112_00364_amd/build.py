@@ -32,7 +32,7 @@ def command(out: str = LIB) -> list[str]:
 
 def build(verbose: bool = False) -> str:
     """Always recompiles; writes the library atomically."""
-    tmp = LIB + ".tmp"
+    tmp = f"{LIB}.{os.getpid()}.tmp"  # per process: concurrent builds do not collide
     r = subprocess.run(command(tmp), capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stderr[-4000:])
