@@ -487,6 +487,9 @@ def main():
     ap.add_argument("--no-tail-call", action="store_true",
                     help="compiled-program point: skip the tail-call form (profiles of the stack-growing form)")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
+    ap.add_argument("--only", choices=["ess", "crbd_ds", "seir", "seir_program", "bucketing"],
+                    help="run this one leg alone (no headline runs) and print its record: "
+                         "for kernel traces that hold one workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 256 MiB device-to-device 3 times (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -513,6 +516,15 @@ def main():
     spec = I.crbd_spec(tree, precision=32)
     rounds = 2 * TIPS - 1
     ctx = smc.Context(0)
+    if args.only:
+        legs = {"ess": lambda: ess_point(smc, ctx, spec, N_PARTICLES),
+                "crbd_ds": lambda: crbd_ds_point(smc, ctx, I, tree, N_PARTICLES),
+                "seir": lambda: seir_point(smc, ctx, I, cpu=False),
+                "seir_program": lambda: seir_program_point(smc, ctx, I),
+                "bucketing": lambda: bucketing_point(smc, ctx, I)}
+        print(f"{args.only} leg alone", file=sys.stderr, flush=True)
+        print(json.dumps({"leg": args.only, args.only: legs[args.only]()}), flush=True)
+        return
     model = smc.Model(ctx, spec)
     stream = ctx.stream
     # One run's buffers, reused: smc_reset re-initialises them on the device and
