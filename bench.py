@@ -119,6 +119,39 @@ def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16):
             "block_steps_per_s": total / dt, "finished_runs": ok, "rounds_per_tick": rounds_per_tick}
 
 
+def _clads_oracle_run(job):
+    """One run of the ClaDS batch (run index r, tips) on the CPU oracle, in a worker process."""
+    r, tips, n = job
+    from oracle import oracle as O
+    from paper_2112_00364_amd import inputs as I
+    run = O.Run(I.clads_spec(I.yule_tree(tips, 4000 + r), precision=32), n, 40000 + r)
+    st = run.run_to_end()
+    return st == O.FINISHED, run.block_steps
+
+
+def batched_clads_cpu(runs_per_worker: int = 2, n: int = 4096, max_workers: int = 16):
+    """The batched ClaDS workload on the host: its first runs (same trees and seeds),
+    each an independent oracle process, on every host core available to this
+    process (at most `max_workers`). Aggregate block-steps/s over the wall time."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle import oracle as O
+    O.build()
+    workers = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    tips = np.random.default_rng(4000).integers(32, 129, size=512)
+    jobs = [(r, int(tips[r]), n) for r in range(workers * runs_per_worker)]
+    t0 = time.perf_counter()
+    # fresh interpreters (not forks of this process, which holds a GPU context)
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_clads_oracle_run, jobs, chunksize=1)
+    dt = time.perf_counter() - t0
+    assert all(ok for ok, _ in res)
+    steps = sum(s for _, s in res)
+    return {"value": steps / dt, "unit": "particle-block-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"runs 0-{len(jobs) - 1} of the ClaDS batch ({n} particles each), one oracle process "
+                      f"per run, {workers} processes, {dt:.1f} s"}
+
+
 def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers):
     """Serving stream: calibrate the one-at-a-time service rate on the first
     requests, then for each multiplier m replay the same requests with Poisson
@@ -652,6 +685,9 @@ def main():
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_particles)
+        if "batched" in out:
+            print("cpu baseline of the batched leg (all cores)", file=sys.stderr, flush=True)
+            out["batched"]["cpu_oracle_all_cores"] = batched_clads_cpu()
     print(json.dumps(out))
     model.close()
     ctx.close()
