@@ -129,7 +129,7 @@ def _clads_oracle_run(job):
     return st == O.FINISHED, run.block_steps
 
 
-def batched_clads_cpu(runs_per_worker: int = 2, n: int = 4096, max_workers: int = 16):
+def batched_clads_cpu(runs_per_worker: int = 8, n: int = 4096, max_workers: int = 16):
     """The batched ClaDS workload on the host: its first runs (same trees and seeds),
     each an independent oracle process, on every host core available to this
     process (at most `max_workers`). Aggregate block-steps/s over the wall time."""
