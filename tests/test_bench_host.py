@@ -1,0 +1,60 @@
+"""Host-side logic of bench.py: the algorithmic byte counts the roofline divides
+by, the rule that ties a counter record to the kernel sources, the refusal of
+more than one GPU, and the all-cores oracle sample of the batched leg."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_algorithmic_bytes_per_round():
+    # Per particle and round: propagate reads anc 4 + block 1 + (lambda, mu) 8 and
+    # writes block 1 + (lambda, mu) 8 + lw 8 = 30 B (round 0 has nothing to gather:
+    # 17 B); reduce reads lw 8 (+16 B per 1024-particle tile); scan reads lw 8 and
+    # writes anc 4, except in the final round.
+    n, rounds = 1 << 20, 511
+    run_total = bench.bytes_per_launch("propagate", n, rounds) * rounds
+    assert run_total == pytest.approx(n * (17 + 30 * (rounds - 1)), rel=1e-12)
+    assert bench.bytes_per_launch("reduce", n, rounds) == n * 8 + (n // 1024) * 16
+    assert bench.bytes_per_launch("scan_anc", n, rounds) * rounds == pytest.approx(n * 12 * (rounds - 1), rel=1e-12)
+    # the headline launch figure quoted with the roofline: 31.4 MB per propagation launch
+    assert bench.bytes_per_launch("propagate", n, rounds) == pytest.approx(31.43e6, rel=1e-3)
+
+
+def test_traffic_record_only_for_current_kernels(tmp_path, monkeypatch):
+    os.makedirs(tmp_path / "profiles")
+    rec = {"kernels": {"propagate": {"hbm_bytes_per_launch": 123.0}}, "source_sha": "aaaa"}
+    (tmp_path / "profiles" / "t.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "aaaa")
+    assert bench.measured_traffic("propagate", 1.0, "t.json") == 123.0
+    assert bench.measured_traffic("reduce", 1.0, "t.json") is None      # kernel not in the record
+    assert bench.measured_traffic("propagate", 1.0, "none.json") is None  # no record
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "bbbb")
+    assert bench.measured_traffic("propagate", 1.0, "t.json") is None   # kernels changed since
+
+
+def test_kernel_source_hash_ignores_host_engine():
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_batched_leg_cpu_sample(oracle):
+    out = bench.batched_clads_cpu(runs_per_worker=1, n=256, max_workers=2)
+    assert out["kind"] == "oracle" and out["unit"] == "particle-block-steps/s"
+    assert 1 <= out["cores"] <= 2 and out["value"] > 0
+    assert "one oracle process per run" in out["sample"]
+    assert 0 <= out["finished_runs"] <= 2
