@@ -220,10 +220,30 @@ def test_algorithm2_preserves_execution_order(seed):
     ("(program (def main () (observe gamma 1 1 1)))", "bad observe"),
     ("(program (def main () (let a (at nothere 0))))", "unknown data"),
     ("(program (def main () (let a (+ 1 2 3))))", "two operands"),
+    ("(program (def main () (let a (+ 1))))", "two operands"),
+    ("(program (def main () (let a (neg 1 2))))", "one operand"),
+    ("(program (def main () (let a ())))", "empty expression"),
+    ("(program (def main () (return 0))", "missing"),
+    ("(program (def main () (return 0))))", "text after the program"),
+    ("(prog (def main () (return 0)))", "starts with"),
+    ("(program (def main () (return 0)) (def main () (return 0)))", "defined twice"),
+    ("(program (data y 1 a) (def main () (return 0)))", "non-number"),
+    ("(program (def main () (frobnicate 1)))", "unknown statement"),
+    ("(program (def main () " + "(resample) " * 300 + "(return 0)))", "at most 254"),
 ])
 def test_compiler_rejects(text, msg):
     with pytest.raises(ppl.CompileError, match=msg):
         ppl.compile_program(text)
+
+
+def test_frame_larger_than_the_stack_is_rejected():
+    # values live across the checkpoint go to the frame; 16 words cannot hold them
+    lets = " ".join(f"(let v{i} {i})" for i in range(40))
+    uses = " ".join(f"(let w{i} (+ v{i} 1))" for i in range(40))
+    text = f"(program (def main () {lets} (resample) {uses} (return 0)))"
+    with pytest.raises(ppl.CompileError, match="exceeds the stack"):
+        ppl.compile_program(text, stack_words=16)
+    assert ppl.compile_program(text, stack_words=256).stack_words == 256
 
 
 def test_frames_and_inlining():
