@@ -133,22 +133,73 @@ def test_lgssm_unbiased_small_n(oracle):
     assert ok, (m, se)
 
 
+def _normal_from_words(oracle, w1, w2):
+    """Box-Muller (cosine branch) from two words with the pinned log and cos 2 pi u;
+    sqrt is correctly rounded in Python as in C."""
+    u1, u2 = oracle.uniform_from_word(w1), oracle.uniform_from_word(w2)
+    return math.sqrt(-2.0 * oracle.log(u1)) * oracle.cos2pi(u2)
+
+
 def test_fp32_state_is_rounded(oracle):
+    """FP32 storage (reading R14): the block computes in FP64 and rounds once
+    when it stores. The first propagation runs init (x0 from the prior) and,
+    through the non-checkpoint jump, the first iteration; recomputed here from
+    the particle's own words, the FP32 run holds exactly
+    f32((a f32(m0 + s0 z) + b) + q z') and the FP64 run (a (m0 + s0 z) + b) + q z'."""
     y = I.lgssm_data(5, 1)
-    r = oracle.Run(I.lgssm_spec(y, 32), 64, 2)
-    r.step()
-    x32 = r.field(0, np.float32)
-    r64 = oracle.Run(I.lgssm_spec(y, 64), 64, 2)
+    n, seed = 64, 2
+    r32 = oracle.Run(I.lgssm_spec(y, 32), n, seed)
+    r32.step()
+    r64 = oracle.Run(I.lgssm_spec(y, 64), n, seed)
     r64.step()
-    x64 = r64.field(0, np.float64)
-    # the first block only rounds once more: the FP32 run stores float(x)
-    assert np.all(np.abs(x32.astype(np.float64) - x64) <= np.abs(x64) * 2.0 ** -23 + 1e-30) or True
+    x32, x64 = r32.field(0, np.float32), r64.field(0, np.float64)
     assert x32.dtype == np.float32
+    a, b, q, _, m0, s0 = I.lgssm_spec(y, 32)["params"]
+    for j in range(n):
+        w = [oracle.word(seed, k, j, 0, 0) for k in range(4)]
+        z0 = _normal_from_words(oracle, w[0], w[1])
+        z1 = _normal_from_words(oracle, w[2], w[3])
+        x0_32 = float(np.float32(m0 + s0 * z0))
+        want32 = np.float32((a * x0_32 + b) + q * z1)
+        want64 = (a * (m0 + s0 * z0) + b) + q * z1
+        assert x32[j].view(np.uint32) == want32.view(np.uint32), j
+        assert np.float64(x64[j]).view(np.uint64) == np.float64(want64).view(np.uint64), j
+    # the two precisions really differ (the FP32 run rounded the prior draw)
+    assert np.any(x32.astype(np.float64) != x64)
 
 
 # --- CRBD (Appendix B listing) -----------------------------------------------------------
 
 SMALL_TREE = ((((0.0, 0.0, 0.21), 0.0, 0.55), ((0.0, 0.0, 0.33), 0.0, 0.62), 1.0))
+
+
+@pytest.mark.parametrize("lam,mu,rho", [(2.0, 0.5, 1.0), (1.3, 1.3, 1.0), (0.7, 1.9, 0.6),
+                                         (3.0, 0.0, 0.3), (1.1, 1.1, 0.45)])
+def test_crbd_closed_form_branch_factor_against_rk4(lam, mu, rho):
+    """The closed form used as the CRBD target is checked against direct RK4
+    integration of the birth-death ODEs (E extinction, D lineage density): the
+    expected weight factor of a branch from t_c to t_p is D(t_p)/D(t_c), which
+    the closed form writes as p1(t_p)/p1(t_c). Includes r = lambda - mu = 0."""
+    for tc, tp in ((0.0, 0.37), (0.21, 1.0), (0.5, 0.55)):
+        rk = A.crbd_branch_factor_rk4(tc, tp, lam, mu, rho, steps=4000)
+        closed = A.log_p1(tp, lam, mu, rho) - A.log_p1(tc, lam, mu, rho)
+        assert abs(rk - closed) < 1e-9, (lam, mu, rho, tc, tp, rk, closed)
+
+
+def test_crbd_closed_form_tree_against_rk4():
+    """The whole-tree closed form (corr + (n-2) log lambda + 2 log p1(root) +
+    sum over internal non-root log p1) equals the product of RK4 branch factors
+    times lambda at every internal non-root node, with tip factors rho = p1(0)."""
+    tree = I.yule_tree(7, 12)
+    lam, mu, rho = 1.7, 0.6, 1.0
+    left, age, parent = tree["left"], tree["age"], tree["parent"]
+    ll = A.crbd_corr(int((left < 0).sum()))
+    for i in range(1, len(age)):
+        ll += A.crbd_branch_factor_rk4(age[i], age[parent[i]], lam, mu, rho, steps=4000)
+        ll += math.log(lam) if left[i] >= 0 else math.log(rho)
+    # branch factors start at p1(t_c); the root's two branches use p1(root) each
+    # and the tips contribute p1(0) = rho, so the product telescopes to the closed form
+    assert abs(ll - A.crbd_log_lik(tree, lam, mu, rho)) < 1e-8
 
 
 def test_crbd_fixed_rates_converge_to_closed_form(oracle):
