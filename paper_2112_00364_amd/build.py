@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpcfgsmc.so")
 SOURCES = ["kernels.hip", "capi.hip"]
-HEADERS = ["devmath.hpp", "models.hpp", "engine.hpp", "launch.hpp"]
+HEADERS = ["devmath.hpp", "models.hpp", "engine.hpp", "launch.hpp", "program.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

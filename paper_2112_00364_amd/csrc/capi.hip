@@ -1065,6 +1065,26 @@ struct smc_batch {
 
 namespace {
 
+// Drops the device tables and the host lists they were built from; the next
+// tick rebuilds them (dirty stays set).
+void clear_tables(smc_batch* b)
+{
+    b->tables.release_all();
+    b->runs = nullptr;
+    b->red_tiles = nullptr;
+    b->n_red = 0;
+    b->groups.clear();
+    b->runs_h.clear();
+    b->group_tiles_h.clear();
+    b->red_tiles_h.clear();
+    b->any_unfused = false;
+    b->dirty = true;
+}
+
+// Rebuilds the (run, tile) tables of the live runs. The batch counts as
+// rebuilt (dirty cleared) only once every table is on the device: after a
+// failed allocation or copy the tables are released and the next tick
+// rebuilds them from scratch, so no kernel ever sees a partial table.
 smc_status rebuild_tables(smc_batch* b)
 {
     hipStream_t st = b->ctx->stream;
@@ -1074,12 +1094,7 @@ smc_status rebuild_tables(smc_batch* b)
         b->graph = nullptr;
     }
     b->same_ticks = 0;
-    b->tables.release_all();
-    b->groups.clear();
-    b->runs_h.clear();
-    b->group_tiles_h.clear();
-    b->red_tiles_h.clear();
-    b->any_unfused = false;
+    clear_tables(b);
     struct Key {
         int kind, precision;
     };
@@ -1099,22 +1114,33 @@ smc_status rebuild_tables(smc_batch* b)
         for (uint32_t t = 0; t < r->n_prop; ++t) b->group_tiles_h[g].push_back(TileRef{idx, t});
         for (uint32_t t = 0; t < r->n_red; ++t) b->red_tiles_h.push_back(TileRef{idx, t});
     }
-    b->dirty = false;
-    if (b->runs_h.empty()) return SMC_OK;
+    if (b->runs_h.empty()) {
+        b->dirty = false;
+        return SMC_OK;
+    }
+    auto undo = [&](smc_status s) {
+        clear_tables(b);
+        return s;
+    };
     b->runs = (RunDev*)b->tables.get(sizeof(RunDev) * b->runs_h.size());
     b->red_tiles = (TileRef*)b->tables.get(sizeof(TileRef) * b->red_tiles_h.size());
-    if (!b->runs || !b->red_tiles) return fail(SMC_ERR_OOM, "batch table allocation failed");
-    HIP_TRY(hipMemcpyAsync(b->runs, b->runs_h.data(), sizeof(RunDev) * b->runs_h.size(), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(b->red_tiles, b->red_tiles_h.data(), sizeof(TileRef) * b->red_tiles_h.size(),
-                           hipMemcpyHostToDevice, st));
-    b->n_red = (uint32_t)b->red_tiles_h.size();
+    if (!b->runs || !b->red_tiles) return undo(fail(SMC_ERR_OOM, "batch table allocation failed"));
+    hipError_t e = hipMemcpyAsync(b->runs, b->runs_h.data(), sizeof(RunDev) * b->runs_h.size(),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->red_tiles, b->red_tiles_h.data(), sizeof(TileRef) * b->red_tiles_h.size(),
+                           hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return undo(fail(SMC_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e)));
     for (size_t g = 0; g < keys.size(); ++g) {
         TileRef* t = (TileRef*)b->tables.get(sizeof(TileRef) * b->group_tiles_h[g].size());
-        if (!t) return fail(SMC_ERR_OOM, "batch table allocation failed");
-        HIP_TRY(hipMemcpyAsync(t, b->group_tiles_h[g].data(), sizeof(TileRef) * b->group_tiles_h[g].size(),
-                               hipMemcpyHostToDevice, st));
+        if (!t) return undo(fail(SMC_ERR_OOM, "batch table allocation failed"));
+        e = hipMemcpyAsync(t, b->group_tiles_h[g].data(), sizeof(TileRef) * b->group_tiles_h[g].size(),
+                           hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return undo(fail(SMC_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e)));
         b->groups.push_back(smc_batch::Group{keys[g].kind, keys[g].precision, t, (uint32_t)b->group_tiles_h[g].size()});
     }
+    b->n_red = (uint32_t)b->red_tiles_h.size();
+    b->dirty = false;
     return SMC_OK;
 }
 

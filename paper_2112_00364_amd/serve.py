@@ -104,11 +104,14 @@ def serve_one_at_a_time(ctx: smc.Context, reqs, honour_arrivals=True, log_every=
 
 def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: int = 8,
                   max_live: int = 256, honour_arrivals=True, log_every=100):
-    """Continuous batching: admit while memory and slots allow, tick, retire."""
+    """Continuous batching: admit while memory and slots allow, tick, retire.
+    An admission whose allocation fails (SMC_ERR_OOM) waits for the next
+    retirement and is tried again; serve_batched.last_oom_waits counts them."""
     pending = collections.deque(sorted(reqs, key=lambda r: r["arrival"]))
     batch = smc.Batch(ctx)
     live = {}       # slot -> (request, model, admitted time)
     used = 0
+    oom_waits = 0   # admissions postponed because an allocation failed
     out = []
     t0 = time.perf_counter()
     while pending or live:
@@ -118,9 +121,20 @@ def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: i
             r = pending[0]
             if live and (used + r["bytes"] > memory_budget or len(live) >= max_live):
                 break
+            model = None
+            try:
+                model = smc.Model(ctx, r["spec"])
+                slot = batch.add(model, r["n"], r["seed"])
+            except smc.SMCError as e:
+                if model is not None:
+                    model.close()
+                # the device is fuller than the budget says: wait for live runs
+                # to retire and try again (a request that fails alone cannot fit)
+                if e.code != smc.ERR_OOM or not live:
+                    raise
+                oom_waits += 1
+                break
             pending.popleft()
-            model = smc.Model(ctx, r["spec"])
-            slot = batch.add(model, r["n"], r["seed"])
             live[slot] = (r, model, time.perf_counter() - t0)
             used += r["bytes"]
         if not live:
@@ -141,6 +155,7 @@ def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: i
                 if log_every and len(out) % log_every == 0:
                     _progress(f"batched: {len(out)}/{len(reqs)} done, {len(live)} live at {now:.1f} s")
     batch.close()
+    serve_batched.last_oom_waits = oom_waits
     return out, time.perf_counter() - t0
 
 

@@ -179,7 +179,10 @@ def _torch():
 class Context:
     """One device and one HIP stream; device memory from torch's caching allocator."""
 
-    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = True, allocator=None):
+        """allocator: optional (alloc(nbytes) -> device address or None, free(address))
+        pair used instead of torch's caching allocator (None from alloc is an
+        allocation failure, which the library reports as ERR_OOM)."""
         torch = _torch()
         L = lib()
         self.device = device
@@ -187,7 +190,21 @@ class Context:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self._alloc_ref = None
         alloc_ptr = None
-        if torch_allocator:
+        if allocator is not None:
+            user_alloc, user_free = allocator
+
+            def _a(_ctx, nbytes):
+                try:
+                    return user_alloc(int(nbytes))
+                except Exception:
+                    return None
+
+            def _f(_ctx, p):
+                user_free(p)
+
+            self._alloc_ref = _Allocator(_ALLOC(_a), _FREE(_f), None)
+            alloc_ptr = C.cast(C.pointer(self._alloc_ref), C.c_void_p)
+        elif torch_allocator:
             dev, strm = device, self.stream
 
             def _a(_ctx, nbytes):

@@ -101,3 +101,11 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(smc, "LIB_PATH", str(tmp_path / "absent.so"))
     with pytest.raises(RuntimeError):
         smc.lib()
+
+
+def test_stale_library_check_watches_every_source():
+    """sources_newer_than_lib() (which decides whether the tests rebuild) must
+    look at every source and header the library is compiled from."""
+    from paper_2112_00364_amd import build as B
+    on_disk = sorted(f for f in os.listdir(B.CSRC) if f.endswith((".hip", ".hpp", ".h")))
+    assert sorted(B.SOURCES + B.HEADERS) == on_disk
