@@ -346,6 +346,19 @@ smc_status smc_profile_read(smc_run* run, smc_kernel_times* out);
 smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint64_t seed,
                                 uint32_t round, uint32_t* anc, double* logz_inc);
 
+/* smc_resample_weights for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same results and status codes, the same
+ * kernels, but no hipMalloc, hipFree or allocator call. Its control block,
+ * group slots and per-tile partials live in a static device array of about
+ * 390 KB that each GPU holds from smc_ctx_create (which looks up its address)
+ * until the process ends; n is limited to 2^24 (SMC_ERR_INVALID beyond). Every
+ * call on one GPU shares that array and re-initialises it on the device, so
+ * calls on one GPU must not overlap (two streams or threads at once race).
+ * Synchronises with the context stream. */
+smc_status smc_resample_weights_noalloc(smc_ctx* ctx, const double* lw, uint64_t n, uint64_t seed,
+                                        uint32_t round, uint32_t* anc, double* logz_inc);
+
 /* Batches: many independent runs advanced together (one launch per kernel
  * for all runs; small runs run whole rounds inside one work-group).
  * Results are identical to the same runs executed alone. */

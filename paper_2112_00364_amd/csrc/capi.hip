@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -43,11 +44,49 @@ smc_status fail(smc_status code, const std::string& msg)
 
 constexpr uint64_t kMaxParticles = 1ull << 24;
 
+// Device memory of smc_resample_weights_noalloc: control block, propagation
+// group slots and three per-tile partial arrays for up to kMaxParticles
+// weights, carved from one static device array. Every GPU the library runs on
+// holds its own copy (about 390 KB) until the process ends; host code reaches
+// it only through the address hipGetSymbolAddress returns on that device.
+constexpr size_t kNoallocCtlOff = 0;
+constexpr size_t kNoallocGroupsOff = 256;
+constexpr size_t kNoallocMaxTiles = (kMaxParticles + kTileRed - 1) / kTileRed;
+constexpr size_t kNoallocPartOff = kNoallocGroupsOff + ((sizeof(GroupPartials) + 255) / 256) * 256;
+constexpr size_t kNoallocPartBytes = kNoallocMaxTiles * sizeof(double);
+constexpr size_t kNoallocBytes = kNoallocPartOff + 3 * kNoallocPartBytes;
+static_assert(sizeof(RunCtl) <= kNoallocGroupsOff, "control block fits its slot");
+static_assert(kNoallocPartBytes % 256 == 0, "partial arrays stay 256-byte aligned");
+
+__device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up this device's copy of the array once per device (the device must
+// be current) and keeps its address.
+smc_status scratch_address(int device, void** out)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(SMC_ERR_INVALID, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SMC_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return SMC_OK;
+}
+
 }  // namespace
 
 struct smc_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    void* scratch = nullptr;  // this device's copy of the static scratch array
     smc_allocator alloc{};
     bool custom_alloc = false;
 
@@ -434,9 +473,13 @@ smc_status smc_ctx_create(int32_t device, void* stream, const smc_allocator* all
     HIP_TRY(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(SMC_ERR_INVALID, "no such device");
     HIP_TRY(hipSetDevice(device));
+    void* scratch_ptr = nullptr;
+    const smc_status ss = scratch_address(device, &scratch_ptr);
+    if (ss != SMC_OK) return ss;
     smc_ctx* c = new (std::nothrow) smc_ctx();
     if (!c) return fail(SMC_ERR_OOM, "host allocation failed");
     c->device = device;
+    c->scratch = scratch_ptr;
     c->stream = (hipStream_t)stream;
     if (allocator) {
         c->alloc = *allocator;
@@ -1027,6 +1070,34 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
     arena.release_all();
     if (e != hipSuccess) return fail(SMC_ERR_DEVICE, hipGetErrorString(e));
     return c.status;
+}
+
+smc_status smc_resample_weights_noalloc(smc_ctx* ctx, const double* lw, uint64_t n, uint64_t seed, uint32_t round,
+                                        uint32_t* anc, double* logz_inc)
+{
+    if (!ctx || !lw || !anc || !logz_inc) return fail(SMC_ERR_INVALID, "NULL argument");
+    if (n == 0 || n > kMaxParticles) return fail(SMC_ERR_INVALID, "n must be in [1, 2^24]");
+    if (!ctx->scratch) return fail(SMC_ERR_STATE, "context has no scratch address");
+    unsigned char* base = static_cast<unsigned char*>(ctx->scratch);
+    RunDev h{};
+    h.n = (uint32_t)n;
+    h.red_tiles = (uint32_t)((n + kTileRed - 1) / kTileRed);
+    if (h.red_tiles > kNoallocMaxTiles) return fail(SMC_ERR_INVALID, "n beyond the scratch capacity");
+    set_prop_tiles(h, kMaxkeyThreads);
+    h.lw = const_cast<double*>(lw);
+    h.anc = anc;
+    h.ctl = reinterpret_cast<RunCtl*>(base + kNoallocCtlOff);
+    h.groups = reinterpret_cast<GroupPartials*>(base + kNoallocGroupsOff);
+    h.part_q = reinterpret_cast<double*>(base + kNoallocPartOff);
+    h.part_e = reinterpret_cast<double*>(base + kNoallocPartOff + kNoallocPartBytes);
+    h.prefix = reinterpret_cast<double*>(base + kNoallocPartOff + 2 * kNoallocPartBytes);
+    hipStream_t st = ctx->stream;
+    hipError_t e = launch_resample_weights_one(h, round, seed, logz_inc, st);
+    int32_t status = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&status, &h.ctl->status, sizeof(status), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(SMC_ERR_DEVICE, hipGetErrorString(e));
+    return status;
 }
 
 // ---------------------------------------------------------------------------

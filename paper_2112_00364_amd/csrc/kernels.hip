@@ -1004,9 +1004,8 @@ __device__ inline void finish_round(const RunDev& R, RunCtl* ctl, bool bad, bool
 
 // Fold-kernel path (large runs): one work-group per run folds the reduction's
 // tile sums and writes the tile offsets.
-__global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __restrict__ runs)
+__device__ __forceinline__ void fold_sums_body(const RunDev& R)
 {
-    const RunDev& R = runs[blockIdx.x];
     RunCtl* ctl = R.ctl;
     if (ctl->status != 0 || R.fused) return;
     const bool bad = ctl->bad != 0;
@@ -1059,6 +1058,16 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __rest
         ctl->qtot = q_all;
         finish_round(R, ctl, bad, usable, M, e_all, active, resample);
     }
+}
+
+__global__ __launch_bounds__(kFoldThreads) void k_fold_sums(const RunDev* __restrict__ runs)
+{
+    fold_sums_body(runs[blockIdx.x]);
+}
+
+__global__ __launch_bounds__(kFoldThreads) void k_fold_sums_one(const RunDev R)
+{
+    fold_sums_body(R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1269,11 +1278,8 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
 // ---------------------------------------------------------------------------
 // Standalone pieces: max of a given weight vector, reads, self-tests, setup.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kMaxkeyThreads) void k_maxkey(const RunDev* __restrict__ runs,
-                                                          const TileRef* __restrict__ tiles)
+__device__ __forceinline__ void maxkey_body(const RunDev& R, const TileRef tr)
 {
-    const TileRef tr = tiles[blockIdx.x];
-    const RunDev& R = runs[tr.run];
     const uint32_t i = tr.tile * kMaxkeyThreads + threadIdx.x;
     Partial p{0ull, 0u, 0u, 0u};
     if (i < R.n) {
@@ -1284,6 +1290,39 @@ __global__ __launch_bounds__(kMaxkeyThreads) void k_maxkey(const RunDev* __restr
     }
     const Partial r = block_partial<kMaxkeyThreads>(p);
     if (threadIdx.x == 0) publish_group(R, tr.tile, r);
+}
+
+__global__ __launch_bounds__(kMaxkeyThreads) void k_maxkey(const RunDev* __restrict__ runs,
+                                                          const TileRef* __restrict__ tiles)
+{
+    const TileRef tr = tiles[blockIdx.x];
+    maxkey_body(runs[tr.run], tr);
+}
+
+__global__ __launch_bounds__(kMaxkeyThreads) void k_maxkey_one(const RunDev R)
+{
+    maxkey_body(R, TileRef{0u, blockIdx.x});
+}
+
+// Standalone resampling with caller-provided control memory: the control
+// block starts as a fresh run at `round` under `seed`, and the propagation
+// group slots start cleared (a kernel, not a memset, so nothing here depends
+// on what an earlier call left behind).
+__global__ __launch_bounds__(kPartialGroups) void k_resample_prepare(const RunDev R, uint32_t round, uint64_t seed)
+{
+    R.groups->key[threadIdx.x] = 0ull;
+    R.groups->counts[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) {
+        RunCtl c{};
+        c.round = round;
+        c.seed = seed;
+        *R.ctl = c;
+    }
+}
+
+__global__ void k_store_log_z(const RunCtl* __restrict__ ctl, double* __restrict__ out)
+{
+    if (threadIdx.x == 0) *out = ctl->log_z;
 }
 
 // Gathered copy of one array: dst[j] = src[anc[j]] for `levels` level-major rows.
@@ -1491,6 +1530,18 @@ hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st)
 {
     hipLaunchKernelGGL(k_maxkey, dim3(n_tiles), dim3(kMaxkeyThreads), 0, st, runs, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_resample_weights_one(const RunDev& run, uint32_t round, uint64_t seed, double* log_z_out,
+                                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resample_prepare, dim3(1), dim3(kPartialGroups), 0, st, run, round, seed);
+    hipLaunchKernelGGL(k_maxkey_one, dim3(run.prop_tiles), dim3(kMaxkeyThreads), 0, st, run);
+    hipLaunchKernelGGL(k_reduce_one, dim3(run.red_tiles), dim3(kRedThreads), 0, st, run);
+    if (!run.fused) hipLaunchKernelGGL(k_fold_sums_one, dim3(1), dim3(kFoldThreads), 0, st, run);
+    hipLaunchKernelGGL(k_scan_anc_one, dim3(run.red_tiles), dim3(kRedThreads), 0, st, run);
+    hipLaunchKernelGGL(k_store_log_z, dim3(1), dim3(64), 0, st, run.ctl, log_z_out);
     return hipGetLastError();
 }
 

@@ -18,6 +18,12 @@ hipError_t launch_reduce(const RunDev* runs, const TileRef* tiles, uint32_t n_ti
                          bool any_unfused, hipStream_t st);
 hipError_t launch_scan_anc(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
 hipError_t launch_maxkey(const RunDev* runs, const TileRef* tiles, uint32_t n_tiles, hipStream_t st);
+// resampling alone on a run record whose control block, group slots and tile
+// partials sit in caller-provided device memory (no table uploads): prepares
+// the control block, then max, reduction (+ fold), scan and ancestors, and
+// stores the log Z increment at log_z_out
+hipError_t launch_resample_weights_one(const RunDev& run, uint32_t round, uint64_t seed, double* log_z_out,
+                                       hipStream_t st);
 hipError_t launch_gather(int elem_bytes, const void* src, const uint32_t* anc, void* dst, uint64_t n,
                          uint64_t levels, uint64_t stride, hipStream_t st);
 hipError_t launch_selftest_math(int op, const double* in, double* out, uint64_t n, hipStream_t st);

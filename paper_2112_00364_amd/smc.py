@@ -146,6 +146,7 @@ def lib():
         "smc_profile": [vp, i32],
         "smc_profile_read": [vp, C.POINTER(_KernelTimes)],
         "smc_resample_weights": [vp, vp, u64, u64, u32, vp, vp],
+        "smc_resample_weights_noalloc": [vp, vp, u64, u64, u32, vp, vp],
         "smc_batch_create": [vp, C.POINTER(vp)],
         "smc_batch_add": [vp, vp, u64, u64, C.POINTER(i32)],
         "smc_batch_tick": [vp, i32],
@@ -258,6 +259,17 @@ class Context:
                                         C.c_void_p(anc.data_ptr()), C.c_void_p(inc.data_ptr()))
         _check(st, allow=(OK, DEGENERATE, ERR_NAN))
         return st, anc.cpu().numpy().view(np.uint32), float(inc.cpu()[0])
+
+    def resample_weights_noalloc(self, lw_dev, anc_dev, inc_dev, seed: int, rnd: int) -> int:
+        """smc_resample_weights_noalloc on caller-owned device tensors (float64
+        log-weights, int32 ancestors of the same length, one float64 for the log
+        Z increment); the library allocates nothing. Returns the status."""
+        n = lw_dev.numel()
+        if anc_dev.numel() < n or inc_dev.numel() < 1:
+            raise ValueError("output tensors too small")
+        st = lib().smc_resample_weights_noalloc(self._h, C.c_void_p(lw_dev.data_ptr()), n, seed, rnd,
+                                                C.c_void_p(anc_dev.data_ptr()), C.c_void_p(inc_dev.data_ptr()))
+        return _check(st, allow=(OK, DEGENERATE, ERR_NAN))
 
 
 class Model:

@@ -80,6 +80,7 @@ def _null_calls(L):
         "smc_batch_poll": lambda: L.smc_batch_poll(None, 0, None, None, None, None),
         "smc_batch_retire": lambda: L.smc_batch_retire(None, 0),
         "smc_resample_weights": lambda: L.smc_resample_weights(None, None, 10, 1, 0, None, None),
+        "smc_resample_weights_noalloc": lambda: L.smc_resample_weights_noalloc(None, None, 10, 1, 0, None, None),
     }
 
 
