@@ -35,16 +35,25 @@ HBM_PEAK_GBS = 8000.0
 TIPS, TREE_SEED, N_PARTICLES = 256, 3000, 1 << 20
 
 # Algorithmic bytes per launch (FP32 state: lambda, mu), per particle unless noted.
-#  propagate:  anc 4 + gathered block 1 + gathered state 8 read; block 1 + state 8 + lw 8 written
-#              (round 0 only writes: 17)
+#  propagate:  the propagation step (both phases when it is split): anc 4 + gathered block 1 +
+#              gathered state 8 read; block 1 + state 8 + lw 8 written (round 0 only writes: 17).
+#              The hidden-event queue between the phases is the implementation's own traffic.
 #  reduce:     lw 8 read (+ 16 B of tile sums written per 1024-particle tile)
 #  scan_anc:   lw 8 read, anc 4 written (the final round only updates log Z)
+#  resample:   single pass: lw 8 read, anc 4 written (the final round only reads)
 def bytes_per_launch(kernel: str, n: int, rounds: int) -> float:
     if kernel == "propagate":
         return n * (17 + 30 * (rounds - 1)) / rounds
     if kernel == "reduce":
         return n * 8.0 + n / 1024 * 16
+    if kernel == "resample":
+        return n * (8.0 + 4.0 * (rounds - 1) / rounds)
     return n * 12.0 * (rounds - 1) / rounds
+
+
+# Kernels that make up one step of a round: the roofline is taken per step.
+STEPS = {"propagate": ("propagate", "hidden"), "resample": ("resample",), "reduce": ("reduce",),
+         "scan_anc": ("scan_anc",), "bucket": ("bucket",)}
 
 
 def kernel_source_hash() -> str:
@@ -59,17 +68,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n_launch_bytes: float, record: str = "traffic_crbd_yule256_n2p20.json"):
-    """HBM bytes per launch (launches that did work) from a committed rocprofv3
-    counter summary, if it was taken on the current kernel sources; else None."""
+def measured_traffic(step: str, rounds: int, record: str = "traffic_crbd_yule256_n2p20.json"):
+    """HBM bytes per round of one step (all its kernels' dispatches over a
+    run, divided by the run's rounds) from a committed rocprofv3 counter
+    summary of one complete run, if it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("source_sha") != kernel_source_hash() or kernel not in d.get("kernels", {}):
+    ks = d.get("kernels", {})
+    parts = [k for k in STEPS.get(step, (step,)) if k in ks]
+    if d.get("source_sha") != kernel_source_hash() or not parts or any("hbm_bytes_total" not in ks[k] for k in parts):
         return None
-    k = d["kernels"][kernel]
-    return k["hbm_bytes_per_launch"]
+    runs = d.get("runs", 1)
+    return sum(ks[k]["hbm_bytes_total"] for k in parts) / (runs * rounds)
 
 
 def cpu_baseline(spec, n: int):
@@ -85,17 +98,32 @@ def cpu_baseline(spec, n: int):
                       f"single thread, {dt:.1f} s"}
 
 
-def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16):
+def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16, tune=True, cache_path=None):
     """512 independent ClaDS runs (trees of 32-128 tips, seeds 4000 + r), 4096
-    particles each, advanced together by the batch API."""
+    particles each, advanced together by the batch API. Before the timed
+    region the batch autotuner picks each run shape's propagation work-group
+    size (cached in a JSON file, tuned on a probe batch the first time)."""
     import numpy as np
     import torch
+    from paper_2112_00364_amd import autotune as A
     rng = np.random.default_rng(4000)
     tips = rng.integers(32, 129, size=runs)
     models = [smc.Model(ctx, I.clads_spec(I.yule_tree(int(t), 4000 + r), precision=32)) for r, t in enumerate(tips)]
+    lanes = {}
+    tune_s = 0.0
+    cache = A.LaunchCache(cache_path)
+    if tune:
+        t0 = time.perf_counter()
+        for r, t in enumerate(tips):
+            key = A.shape_key("clads", 32, n, int(t))
+            if key not in lanes:
+                lanes[key] = A.batch_workgroup(cache, ctx, models[r], "clads", 32, n, int(t))
+        tune_s = time.perf_counter() - t0
     b = smc.Batch(ctx)
     for r, m in enumerate(models):
-        b.add(m, n, 40000 + r)
+        slot = b.add(m, n, 40000 + r)
+        if tune:
+            b.set_workgroup(slot, lanes[A.shape_key("clads", 32, n, int(tips[r]))])
     b.tick(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -116,7 +144,9 @@ def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16):
         m.close()
     return {"workload": f"clads_batch_{runs}x{n}", "runs": runs, "particles_per_run": n,
             "tips": [int(tips.min()), int(tips.max())], "seconds": dt, "block_steps": total,
-            "block_steps_per_s": total / dt, "finished_runs": ok, "rounds_per_tick": rounds_per_tick}
+            "block_steps_per_s": total / dt, "finished_runs": ok, "rounds_per_tick": rounds_per_tick,
+            "workgroup_lanes": lanes, "autotune": {key: cache.get(key) for key in lanes},
+            "autotune_seconds": tune_s}
 
 
 def _clads_oracle_run(job):
@@ -152,30 +182,44 @@ def batched_clads_cpu(runs_per_worker: int = 8, n: int = 4096, max_workers: int 
             "finished_runs": sum(1 for ok, _ in res if ok)}
 
 
-def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers):
-    """Serving stream: calibrate the one-at-a-time service rate on the first
-    requests, then for each multiplier m replay the same requests with Poisson
-    arrivals at m x that rate through (a) FIFO one-at-a-time plain runs and
-    (b) continuous batching."""
+def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers, alone_path=None, save_alone=None):
+    """Serving stream: every request served alone once, back to back (plain
+    runs, FIFO), which gives its service time, its log Z and the
+    one-at-a-time service rate; then for each multiplier m the same requests
+    arrive (Poisson) at m x that rate and are served (a) one at a time, FIFO:
+    latencies from the measured service times, and (b) by continuous
+    batching, in real time. The back-to-back pass can be saved to a JSON file
+    (save_alone) and read back (alone_path), so that the arrival rates of one
+    stream can be measured in separate processes against one pass."""
     from paper_2112_00364_amd import serve as S
     reqs = S.make_requests(n_requests, 5000, rate_per_s=1.0)
-    calib = reqs[: min(32, len(reqs))]
-    _, t_cal = S.serve_one_at_a_time(ctx, calib, honour_arrivals=False)
-    rate = len(calib) / t_cal
+    if alone_path:
+        rec = json.load(open(alone_path))
+        assert rec["requests"] == n_requests and rec["stream_seed"] == 5000, "pass of another stream"
+        alone, t_alone = rec["served"], rec["seconds"]
+    else:
+        alone, t_alone = S.serve_one_at_a_time(ctx, reqs, honour_arrivals=False)
+        if save_alone:
+            with open(save_alone, "w") as f:
+                json.dump({"requests": n_requests, "stream_seed": 5000, "seconds": t_alone, "served": alone}, f)
+    rate = len(reqs) / t_alone
     out = {"requests": n_requests, "one_at_a_time_service_rate_per_s": rate, "memory_budget_bytes": budget_bytes,
-           "by_arrival_rate": []}
+           "one_at_a_time_latencies": "FIFO over the measured service times of the back-to-back pass",
+           "one_at_a_time_pass": alone_path or "measured in this process", "by_arrival_rate": []}
     for m in multipliers:
         arr = m * rate
         S.rescale_arrivals(reqs, arr, 5001)
         print(f"serving: one-at-a-time rate {rate:.2f}/s, arrivals at {arr:.2f}/s", file=sys.stderr, flush=True)
-        base, t_base = S.serve_one_at_a_time(ctx, reqs)
+        base, t_base = S.fifo_replay(alone, reqs)
         bat, t_bat = S.serve_batched(ctx, reqs, budget_bytes)
         same = {r["id"]: r["log_z"] for r in base}
         worst = max(abs(r["log_z"] - same[r["id"]]) / max(1.0, abs(same[r["id"]])) for r in bat)
+        identical = all(r["log_z"] == same[r["id"]] for r in bat)
         out["by_arrival_rate"].append({"multiplier": m, "arrival_rate_per_s": arr,
                                        "one_at_a_time": S.summarize(base, t_base),
                                        "batched": S.summarize(bat, t_bat),
-                                       "max_rel_logz_diff_batched_vs_alone": worst})
+                                       "max_rel_logz_diff_batched_vs_alone": worst,
+                                       "identical_log_z_batched_vs_alone": identical})
     return out
 
 
@@ -205,7 +249,7 @@ def ess_point(smc, ctx, spec, n: int, tau: float = 0.5, runs: int = 3):
             "block_steps_per_s": s["block_steps"] / (ms / 1e3), "log_z_last": s["log_z"]}
 
 
-def seir_point(smc, ctx, I, n: int = 1 << 16, days: int = 100, runs: int = 3, cpu: bool = True):
+def seir_point(smc, ctx, I, n: int = 1 << 18, days: int = 100, runs: int = 3, cpu: bool = True):
     """The vector-borne disease (SEIR) model of the paper's second experiment
     on a synthetic 100-day outbreak (the dengue data is not available), with
     the listing's priors: complete runs on the GPU, and the oracle on a
@@ -321,7 +365,7 @@ def program_point(smc, ctx, I, n: int = 1 << 20, T: int = 100, runs: int = 2, cp
                              "achieved": round(per_round / us / 1e3, 1), "peak": 8000.0, "unit": "GB/s",
                              "frac": round(per_round / us / 1e3 / 8000.0, 4),
                              "algorithmic_bytes_per_round": per_round,
-                             "traffic": measured_traffic("propagate_program", per_round,
+                             "traffic": measured_traffic("propagate_program", T,
                                                          "traffic_program_lgssm100_n2p20.json")}})
     if cpu:
         from oracle import ppl_oracle as PO
@@ -474,9 +518,145 @@ def crbd_ds_point(smc, ctx, I, tree, n: int, tau: float = 0.5, runs: int = 3):
             "block_steps_per_s": s["block_steps"] / (ms / 1e3), "log_z_last": s["log_z"]}
 
 
-def large_point(smc, model, n: int, runs: int = 2):
+def profile_steps(smc, model, n: int, seed: int, ms_per_run: float, byte_model: dict):
+    """One profiled complete run (HIP events on the run's stream around every
+    launch). Each bracketed launch pays a fixed event cost that the graph replay
+    of the timed runs does not; it is estimated live as (bracketed time of the
+    run - timed time per run) / launches and taken off every launch (the raw
+    figures are kept beside). Returns the per-launch table, the per-step table
+    (a split propagation is two launches per round) and the roofline of the
+    dominant step; byte_model maps a step to its algorithmic bytes per round."""
+    prof = smc.Run(model, n, seed)
+    prof.profile(True)
+    prof.run_to_end()
+    times = prof.kernel_times()
+    prof.close()
+    launched = {k: v for k, v in times.items() if v[1] > 0}
+    bracketed_ms = sum(ms for ms, _ in launched.values())
+    n_launches = sum(c for _, c in launched.values())
+    overhead_ms = max(0.0, (bracketed_ms - ms_per_run) / n_launches)
+    kernels = {}
+    for k, (ms, launches) in launched.items():
+        raw_ms = ms / launches
+        avg_ms = max(raw_ms - overhead_ms, 1e-6)
+        kernels[k] = {"avg_us": avg_ms * 1e3, "bracketed_avg_us": raw_ms * 1e3,
+                      "bracket_overhead_us": overhead_ms * 1e3, "launches": launches}
+    steps = {}
+    for step, parts in STEPS.items():
+        got = [kernels[p] for p in parts if p in kernels]
+        if not got:
+            continue
+        rounds_run = got[0]["launches"]
+        avg_us = sum(g["avg_us"] * g["launches"] for g in got) / rounds_run
+        entry = {"kernels": [p for p in parts if p in kernels], "avg_us_per_round": avg_us, "rounds": rounds_run}
+        if step in byte_model:
+            b = byte_model[step]
+            entry.update({"alg_bytes_per_round": b, "achieved_GBs": b / (avg_us * 1e-6) / 1e9})
+        steps[step] = entry
+    dom = max((k for k in steps if "achieved_GBs" in steps[k]),
+              key=lambda k: steps[k]["avg_us_per_round"] * steps[k]["rounds"])
+    kd = steps[dom]
+    roofline = {"bound": "hbm", "achieved": round(kd["achieved_GBs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
+                "launches_per_round": kd["kernels"], "avg_launch_us": round(kd["avg_us_per_round"], 3)}
+    return {"launches": kernels, "steps": steps}, roofline
+
+
+def kalman_evidence(y, a=0.9, b=0.0, q=1.0, r=0.5, m0=0.0, s0=None) -> float:
+    """Exact log evidence of the 1-D linear-Gaussian model by the Kalman
+    filter (the reference the filter's log Z estimate approaches)."""
+    if s0 is None:
+        s0 = math.sqrt(q * q / (1.0 - a * a))
+    m, P, lz = m0, s0 * s0, 0.0
+    for yt in y:
+        m, P = a * m + b, a * a * P + q * q
+        S = P + r * r
+        lz += -0.5 * (math.log(2.0 * math.pi * S) + (yt - m) ** 2 / S)
+        K = P / S
+        m, P = m + K * (yt - m), (1.0 - K) * P
+    return lz
+
+
+def kalman_point(smc, ctx, I, n: int = 1 << 16, T: int = 100, runs: int = 20):
+    """The linear-Gaussian configuration: T = 100 observations simulated from
+    the model (data seed 2000), 2^16 particles, FP32 state, FP64 log-weights,
+    resampling every step. Complete runs replayed from a captured graph; log Z
+    next to the exact Kalman evidence; the roofline of the dominant step."""
+    import torch
+    y = I.lgssm_data(T, 2000)
+    model = smc.Model(ctx, I.lgssm_spec(y, 32))
+    run = smc.Run(model, n, 1)
+    run.run_to_end()
+    for i in range(3):
+        run.reset(300 + i)
+        run.run_to_end()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    for i in range(runs):
+        run.reset(1 + i)
+        run.run_to_end()
+    end.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / runs
+    s = run.stats()
+    run.close()
+    # per particle and round: anc 4 + gathered block 1 + gathered x 4 read, block 1 + x 4 + lw 8
+    # written (round 0 writes only: 13); resampling reads lw 8 and writes anc 4 (not in the last round)
+    byte_model = {"propagate": n * (13 + 22 * (T - 1)) / T, "resample": n * (8.0 + 4.0 * (T - 1) / T),
+                  "reduce": n * 8.0 + n / 1024 * 16, "scan_anc": n * 12.0 * (T - 1) / T}
+    kernels, roofline = profile_steps(smc, model, n, 4242, ms, byte_model)
+    model.close()
+    exact = kalman_evidence(y)
+    return {"workload": f"lgssm_T{T}_n{n}", "particles": n, "observations": T, "runs": runs, "ms_per_run": ms,
+            "block_steps_per_run": s["block_steps"], "block_steps_per_s": s["block_steps"] / (ms / 1e3),
+            "log_z_last": s["log_z"], "kalman_log_evidence": exact, "roofline": roofline, "kernels": kernels}
+
+
+def small_crbd_point(smc, ctx, I, runs: int = 50, cpu: bool = True):
+    """The small CRBD configuration: 20-tip Yule tree (seed 1000), 1000
+    particles, FP64 throughout: GPU run time and the oracle's time for the same
+    run (single thread, same seed; the two log Z agree)."""
+    import torch
+    tree = I.yule_tree(20, 1000)
+    spec = I.crbd_spec(tree, precision=64)
+    model = smc.Model(ctx, spec)
+    run = smc.Run(model, 1000, 1)
+    run.run_to_end()
+    run.reset(1)
+    run.run_to_end()
+    lz_gpu = run.stats()["log_z"]
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(ctx.stream)
+    for i in range(runs):
+        run.reset(1 + i)
+        run.run_to_end()
+    end.record(ctx.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / runs
+    steps = run.stats()["block_steps"]
+    run.close()
+    model.close()
+    out = {"workload": "crbd_yule20_n1000_fp64", "particles": 1000, "rounds": 39, "ms_per_run": ms,
+           "block_steps_per_s": steps / (ms / 1e3), "log_z_seed1": lz_gpu}
+    if cpu:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        ref = O.Run(spec, 1000, 1)
+        ref.run_to_end()
+        dt = time.perf_counter() - t0
+        out.update({"cpu_oracle_ms_per_run": dt * 1e3, "cpu_oracle_block_steps_per_s": ref.block_steps / dt,
+                    "cpu_oracle_log_z_seed1": ref.log_z, "cpu_oracle_cores": 1})
+    return out
+
+
+def large_point(smc, model, n: int, runs: int = 2, rounds: int = 2 * TIPS - 1, profile: bool = True):
     """Complete runs at a particle count whose buffers exceed the 256 MB
-    Infinity Cache, so every round streams from HBM."""
+    Infinity Cache, so every round streams from HBM; with the roofline of the
+    dominant step (the resampling takes the three-kernel form above 2^20)."""
     import torch
     run = smc.Run(model, n, 77)
     run.run_to_end()
@@ -493,8 +673,14 @@ def large_point(smc, model, n: int, runs: int = 2):
     ms = start.elapsed_time(end) / runs
     s = run.stats()
     run.close()
-    return {"particles": n, "runs": runs, "ms_per_run": ms, "block_steps_per_run": s["block_steps"],
-            "block_steps_per_s": s["block_steps"] / (ms / 1e3)}
+    out = {"particles": n, "runs": runs, "ms_per_run": ms, "block_steps_per_run": s["block_steps"],
+           "block_steps_per_s": s["block_steps"] / (ms / 1e3)}
+    if profile:
+        byte_model = {k: bytes_per_launch(k, n, rounds) for k in ("propagate", "resample", "reduce", "scan_anc")}
+        kernels, roofline = profile_steps(smc, model, n, 79, ms, byte_model)
+        roofline["traffic"] = measured_traffic(roofline["kernel"], rounds, "traffic_crbd_yule256_n2p24.json")
+        out.update({"roofline": roofline, "kernels": kernels})
+    return out
 
 
 def main():
@@ -512,15 +698,26 @@ def main():
     ap.add_argument("--serving-rates", default="0.9",
                     help="arrival rates as multiples of the one-at-a-time service rate, comma-separated")
     ap.add_argument("--no-large", action="store_true", help="skip the 2^24-particle point")
+    ap.add_argument("--no-kalman", action="store_true", help="skip the linear-Gaussian (Kalman) configuration")
+    ap.add_argument("--no-small", action="store_true", help="skip the small CRBD configuration (and its oracle time)")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS-triggered point")
     ap.add_argument("--no-seir", action="store_true", help="skip the vector-borne disease (SEIR) point")
+    ap.add_argument("--seir-particles", type=int, default=1 << 18,
+                    help="particles of the SEIR point (2^16 puts one wavefront on each SIMD)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched leg: keep the default work-group size (no probe batches)")
     ap.add_argument("--no-program", action="store_true", help="skip the compiled-program point")
     ap.add_argument("--no-bucketing", action="store_true", help="skip the block-bucketing point")
     ap.add_argument("--no-crbd-program", action="store_true", help="skip the compiled CRBD point")
     ap.add_argument("--no-tail-call", action="store_true",
                     help="compiled-program point: skip the tail-call form (profiles of the stack-growing form)")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
-    ap.add_argument("--only", choices=["ess", "crbd_ds", "seir", "seir_program", "bucketing"],
+    ap.add_argument("--serving-alone-out", default=None,
+                    help="serving leg: write the back-to-back one-at-a-time pass to this JSON file")
+    ap.add_argument("--serving-alone-in", default=None,
+                    help="serving leg: take the one-at-a-time pass from this JSON file instead of measuring it")
+    ap.add_argument("--only", choices=["ess", "crbd_ds", "seir", "seir_program", "bucketing", "large", "kalman",
+                                       "small", "batched", "serving"],
                     help="run this one leg alone (no headline runs) and print its record: "
                          "for kernel traces that hold one workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -550,11 +747,18 @@ def main():
     rounds = 2 * TIPS - 1
     ctx = smc.Context(0)
     if args.only:
+        rates = [float(x) for x in args.serving_rates.split(",") if x]
         legs = {"ess": lambda: ess_point(smc, ctx, spec, N_PARTICLES),
                 "crbd_ds": lambda: crbd_ds_point(smc, ctx, I, tree, N_PARTICLES),
-                "seir": lambda: seir_point(smc, ctx, I, cpu=False),
+                "seir": lambda: seir_point(smc, ctx, I, n=args.seir_particles, cpu=False),
                 "seir_program": lambda: seir_program_point(smc, ctx, I),
-                "bucketing": lambda: bucketing_point(smc, ctx, I)}
+                "bucketing": lambda: bucketing_point(smc, ctx, I),
+                "large": lambda: large_point(smc, smc.Model(ctx, spec), 1 << 24, runs=1, profile=not args.no_profile),
+                "kalman": lambda: kalman_point(smc, ctx, I),
+                "small": lambda: small_crbd_point(smc, ctx, I, cpu=not args.no_cpu_baseline),
+                "batched": lambda: batched_clads(ctx, smc, I, tune=not args.no_autotune),
+                "serving": lambda: serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30),
+                                           rates, args.serving_alone_in, args.serving_alone_out)}
         print(f"{args.only} leg alone", file=sys.stderr, flush=True)
         print(json.dumps({"leg": args.only, args.only: legs[args.only]()}), flush=True)
         return
@@ -597,35 +801,10 @@ def main():
     roofline = None
     kernels = None
     if not args.no_profile:
-        prof = smc.Run(model, N_PARTICLES, 12345)
-        prof.profile(True)
-        prof.run_to_end()
-        times = prof.kernel_times()
-        prof.close()
-        # Each launch of the profiling pass sits between its own pair of HIP
-        # events, which adds a fixed cost per launch that the graph replay of
-        # the timed runs does not pay. That cost is estimated live: the
-        # bracketed times of one run, less the timed runs' time per run,
-        # spread evenly over the run's launches; it is taken off every
-        # launch (raw bracketed figures are kept beside).
-        launched = {k: v for k, v in times.items() if v[1] > 0}
-        bracketed_ms = sum(ms for ms, _ in launched.values())
-        n_launches = sum(n for _, n in launched.values())
-        overhead_ms = max(0.0, (bracketed_ms - ms_per_step) / n_launches)
-        kernels = {}
-        for k, (ms, launches) in launched.items():
-            raw_ms = ms / launches
-            avg_ms = max(raw_ms - overhead_ms, 1e-6)
-            b = bytes_per_launch(k, N_PARTICLES, rounds)
-            kernels[k] = {"avg_us": avg_ms * 1e3, "bracketed_avg_us": raw_ms * 1e3,
-                          "bracket_overhead_us": overhead_ms * 1e3, "launches": launches,
-                          "alg_bytes_per_launch": b, "achieved_GBs": b / (avg_ms * 1e-3) / 1e9}
-        dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
-        kd = kernels[dom]
-        traffic = measured_traffic(dom, kd["alg_bytes_per_launch"])
-        roofline = {"bound": "hbm", "achieved": round(kd["achieved_GBs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": dom,
-                    "avg_launch_us": round(kd["avg_us"], 3)}
+        byte_model = {k: bytes_per_launch(k, N_PARTICLES, rounds) for k in ("propagate", "resample", "reduce",
+                                                                             "scan_anc")}
+        kernels, roofline = profile_steps(smc, model, N_PARTICLES, 12345, ms_per_step, byte_model)
+        roofline["traffic"] = measured_traffic(roofline["kernel"], rounds)
 
     out = {
         "metric": METRIC,
@@ -649,6 +828,12 @@ def main():
         "wall_s_timed": wall,
         "log_z": log_zs,
     }
+    if not args.no_kalman:
+        print("linear-Gaussian configuration", file=sys.stderr, flush=True)
+        out["kalman"] = kalman_point(smc, ctx, I)
+    if not args.no_small:
+        print("small CRBD configuration", file=sys.stderr, flush=True)
+        out["small"] = small_crbd_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
     if not args.no_ess:
         print("ESS-triggered point", file=sys.stderr, flush=True)
         out["ess"] = ess_point(smc, ctx, spec, N_PARTICLES)
@@ -657,7 +842,7 @@ def main():
         out["crbd_ds"] = crbd_ds_point(smc, ctx, I, tree, N_PARTICLES)
     if not args.no_seir:
         print("SEIR point", file=sys.stderr, flush=True)
-        out["seir"] = seir_point(smc, ctx, I, cpu=not args.no_cpu_baseline)
+        out["seir"] = seir_point(smc, ctx, I, n=args.seir_particles, cpu=not args.no_cpu_baseline)
     if not args.no_program:
         print("compiled-program point", file=sys.stderr, flush=True)
         out["program"] = program_point(smc, ctx, I, cpu=not args.no_cpu_baseline, tail=not args.no_tail_call)
@@ -677,11 +862,12 @@ def main():
         out["large"] = large_point(smc, model, 1 << 24)
     if not args.no_batched:
         print("batched leg", file=sys.stderr, flush=True)
-        out["batched"] = batched_clads(ctx, smc, I)
+        out["batched"] = batched_clads(ctx, smc, I, tune=not args.no_autotune)
     if args.serving_requests > 0:
         print("serving leg", file=sys.stderr, flush=True)
         rates = [float(x) for x in args.serving_rates.split(",") if x]
-        out["serving"] = serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30), rates)
+        out["serving"] = serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30), rates,
+                                 args.serving_alone_in, args.serving_alone_out)
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_particles)

@@ -359,9 +359,13 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
 smc_status smc_resample_weights_noalloc(smc_ctx* ctx, const double* lw, uint64_t n, uint64_t seed,
                                         uint32_t round, uint32_t* anc, double* logz_inc);
 
-/* Batches: many independent runs advanced together (one launch per kernel
- * for all runs; small runs run whole rounds inside one work-group).
- * Results are identical to the same runs executed alone. */
+/* Batches: many independent runs advanced together. Every round of a tick is
+ * one propagation launch per (model kind, precision, work-group size) group
+ * over a (run, tile) table of all live runs, then one reduction and one scan
+ * launch over a table of every run's reduction tiles; each run's tiles read
+ * that run's own control block, so runs of different sizes, trees and round
+ * counts share the launches and finished runs drop out at once. Results are
+ * identical to the same runs executed alone. */
 smc_status smc_batch_create(smc_ctx* ctx, smc_batch** out);
 /* Add a run (Algorithm 1 step 1 for it); *slot receives its index. */
 smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n_particles, uint64_t seed, int32_t* slot);
@@ -369,6 +373,11 @@ smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n_particles, u
  * From the second tick with the same runs and round count on, the tick's
  * launch sequence is captured once into a HIP graph and replayed; adding or
  * retiring a run drops the graph. Results are the same either way. */
+/* Lanes per propagation work-group of the run in `slot` (128 or 256, as
+ * smc_set_workgroup for a single run; a launch option chosen by the
+ * autotuner, results unchanged). The run's tiles move to the launch group of
+ * that size at the next tick. */
+smc_status smc_batch_set_workgroup(smc_batch* b, int32_t slot, int32_t lanes);
 smc_status smc_batch_tick(smc_batch* b, int32_t rounds);
 /* Synchronises. done[i] = 1 for finished (or failed) slots; log_z[i] their
  * estimates; status[i] their status. Arrays are host, length = slots. */

@@ -15,6 +15,10 @@ particles), and the fastest is kept.
 """
 from __future__ import annotations
 
+import json
+import math
+import os
+
 
 def _time_rounds(run, seed: int, rounds: int) -> float:
     import torch
@@ -63,3 +67,86 @@ def choose_bucketing(run, seed: int, rounds: int = 6, repeats: int = 2) -> dict:
     r = choose_launch(run, seed, rounds, repeats, lanes=(None,))
     return {"bucketing": r["bucketing"], "ms_off": r["ms"]["lanesNone_bucketing_off"],
             "ms_on": r["ms"]["lanesNone_bucketing_on"], "rounds": rounds}
+
+
+# --- batches -----------------------------------------------------------------------------
+
+def shape_key(kind: str, precision: int, n: int, tips: int) -> str:
+    """Cache key of a run shape: model kind, precision, particle count (power
+    of two above) and tree size (power of two above; 0 without a tree)."""
+    n2 = 1 << max(0, math.ceil(math.log2(max(n, 1))))
+    t2 = 1 << max(0, math.ceil(math.log2(tips))) if tips else 0
+    return f"{kind}/fp{precision}/n{n2}/tips{t2}"
+
+
+class LaunchCache:
+    """Chosen launch options per run shape, kept in a JSON file: {key:
+    {"lanes": 128|256, "ms": {...}}}. A shape not in the file is timed once
+    (choose_batch_workgroup) and the choice written back."""
+
+    def __init__(self, path: str | None = None):
+        self.path = path or os.path.join(os.path.expanduser("~"), ".cache", "pcfgsmc_launch.json")
+        self.entries = {}
+        if os.path.exists(self.path):
+            try:
+                self.entries = json.load(open(self.path))
+            except (OSError, ValueError):
+                self.entries = {}
+
+    def get(self, key: str):
+        return self.entries.get(key)
+
+    def put(self, key: str, entry: dict):
+        self.entries[key] = entry
+        d = os.path.dirname(self.path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        tmp = f"{self.path}.{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.entries, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
+def choose_batch_workgroup(ctx, model, n: int, seeds, rounds: int = 8, ticks: int = 2,
+                           lanes=(128, 256)) -> dict:
+    """Times a probe batch of len(seeds) runs of `model` (n particles each)
+    advanced `ticks` ticks of `rounds` rounds under each work-group size, from
+    the same initial particles every time (fresh batches, same seeds); the
+    fastest size wins. The probe's results are discarded."""
+    import torch
+    from . import smc
+    times = {}
+    for l in lanes:
+        best = None
+        for _ in range(2):
+            b = smc.Batch(ctx)
+            slots = [b.add(model, n, s) for s in seeds]
+            for slot in slots:
+                b.set_workgroup(slot, l)
+            b.tick(0)  # tables
+            torch.cuda.synchronize()
+            start = torch.cuda.Event(enable_timing=True)
+            end = torch.cuda.Event(enable_timing=True)
+            start.record(ctx.stream)
+            for _ in range(ticks):
+                b.tick(rounds)
+            end.record(ctx.stream)
+            torch.cuda.synchronize()
+            t = start.elapsed_time(end)
+            best = t if best is None else min(best, t)
+            b.close()
+        times[l] = best
+    choice = min(times, key=times.get)
+    return {"lanes": choice, "rounds": rounds, "ticks": ticks, "runs": len(seeds),
+            "ms": {f"lanes{l}": t for l, t in times.items()}}
+
+
+def batch_workgroup(cache: LaunchCache, ctx, model, kind: str, precision: int, n: int, tips: int,
+                    probe_runs: int = 8) -> int:
+    """The cached work-group size for this run shape, tuned on first use."""
+    key = shape_key(kind, precision, n, tips)
+    hit = cache.get(key)
+    if hit is None:
+        hit = choose_batch_workgroup(ctx, model, n, seeds=list(range(90001, 90001 + probe_runs)))
+        cache.put(key, hit)
+    return int(hit["lanes"])

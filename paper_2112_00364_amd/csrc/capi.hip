@@ -1112,7 +1112,7 @@ struct smc_batch {
     DeviceArena tables;
     RunDev* runs = nullptr;
     struct Group {
-        int kind, precision;
+        int kind, precision, lanes;
         TileRef* tiles;
         uint32_t n;
     };
@@ -1167,7 +1167,7 @@ smc_status rebuild_tables(smc_batch* b)
     b->same_ticks = 0;
     clear_tables(b);
     struct Key {
-        int kind, precision;
+        int kind, precision, lanes;
     };
     std::vector<Key> keys;
     for (smc_run* r : b->slots) {
@@ -1176,10 +1176,12 @@ smc_status rebuild_tables(smc_batch* b)
         b->runs_h.push_back(r->host);
         if (!r->host.fused) b->any_unfused = true;
         size_t g = 0;
+        const int lanes = (int)r->host.lanes;
         for (; g < keys.size(); ++g)
-            if (keys[g].kind == r->model->kind && keys[g].precision == r->model->precision) break;
+            if (keys[g].kind == r->model->kind && keys[g].precision == r->model->precision && keys[g].lanes == lanes)
+                break;
         if (g == keys.size()) {
-            keys.push_back(Key{r->model->kind, r->model->precision});
+            keys.push_back(Key{r->model->kind, r->model->precision, lanes});
             b->group_tiles_h.emplace_back();
         }
         for (uint32_t t = 0; t < r->n_prop; ++t) b->group_tiles_h[g].push_back(TileRef{idx, t});
@@ -1208,7 +1210,8 @@ smc_status rebuild_tables(smc_batch* b)
         e = hipMemcpyAsync(t, b->group_tiles_h[g].data(), sizeof(TileRef) * b->group_tiles_h[g].size(),
                            hipMemcpyHostToDevice, st);
         if (e != hipSuccess) return undo(fail(SMC_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e)));
-        b->groups.push_back(smc_batch::Group{keys[g].kind, keys[g].precision, t, (uint32_t)b->group_tiles_h[g].size()});
+        b->groups.push_back(smc_batch::Group{keys[g].kind, keys[g].precision, keys[g].lanes, t,
+                                             (uint32_t)b->group_tiles_h[g].size()});
     }
     b->n_red = (uint32_t)b->red_tiles_h.size();
     b->dirty = false;
@@ -1253,6 +1256,19 @@ smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n, uint64_t se
     return SMC_OK;
 }
 
+smc_status smc_batch_set_workgroup(smc_batch* b, int32_t slot, int32_t lanes)
+{
+    if (!b) return fail(SMC_ERR_INVALID, "NULL batch");
+    if (slot < 0 || (size_t)slot >= b->slots.size() || !b->slots[slot]) return fail(SMC_ERR_INVALID, "no such slot");
+    if (lanes != 128 && lanes != 256) return fail(SMC_ERR_INVALID, "lanes must be 128 or 256");
+    smc_run* r = b->slots[slot];
+    if (r->host.lanes == (uint32_t)lanes) return SMC_OK;
+    const smc_status s = smc_set_workgroup(r, lanes);
+    if (s != SMC_OK) return s;
+    b->dirty = true;  // its tiles move to the group of that size
+    return SMC_OK;
+}
+
 smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
 {
     if (!b || rounds < 0) return fail(SMC_ERR_INVALID, "bad argument");
@@ -1266,7 +1282,7 @@ smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
         const uint32_t n_runs = (uint32_t)b->runs_h.size();
         for (int32_t k = 0; k < rounds; ++k) {
             for (const auto& g : b->groups) {
-                const hipError_t e = launch_propagate(g.kind, g.precision, b->runs, g.tiles, g.n, s);
+                const hipError_t e = launch_propagate(g.kind, g.precision, g.lanes, b->runs, g.tiles, g.n, s);
                 if (e != hipSuccess) return e;
             }
             hipError_t e = launch_reduce(b->runs, b->red_tiles, b->n_red, n_runs, b->any_unfused, s);

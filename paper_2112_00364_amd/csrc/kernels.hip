@@ -751,12 +751,12 @@ __global__ __launch_bounds__(kThreads) void k_propagate_one(const RunDev R)
     propagate_body<Kind, Real, kThreads>(R, blockIdx.x);
 }
 
-template <int Kind, class Real>
-__global__ __launch_bounds__(prop_threads(Kind)) void k_propagate(const RunDev* __restrict__ runs,
-                                                             const TileRef* __restrict__ tiles)
+template <int Kind, class Real, int kThreads>
+__global__ __launch_bounds__(kThreads) void k_propagate(const RunDev* __restrict__ runs,
+                                                        const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
-    propagate_body<Kind, Real, prop_threads(Kind)>(runs[tr.run], tr.tile);
+    propagate_body<Kind, Real, kThreads>(runs[tr.run], tr.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,7 +915,14 @@ __device__ __forceinline__ void reduce_body(const RunDev& R, const TileRef tr)
     const uint32_t base = tr.tile * kTileRed + threadIdx.x * kRedItems;
 #pragma unroll
     for (int k = 0; k < kRedItems; ++k) x[k] = base + k < R.n ? R.lw[base + k] : 0.0;
-    const Partial f = fold_groups(R);
+    // one wavefront folds the run's group slots for the whole work-group
+    __shared__ Partial s_fold;
+    if (threadIdx.x < 64) {
+        const Partial g = fold_groups(R);
+        if (threadIdx.x == 0) s_fold = g;
+    }
+    __syncthreads();
+    const Partial f = s_fold;
     if (status != 0) return;  // uniform over the work-group
     if (tr.tile == 0 && threadIdx.x == 0) publish_fold(R, ctl, f);
     const unsigned long long key = f.key;
@@ -1004,27 +1011,44 @@ __device__ inline void finish_round(const RunDev& R, RunCtl* ctl, bool bad, bool
 
 // Fold-kernel path (large runs): one work-group per run folds the reduction's
 // tile sums and writes the tile offsets.
+// Tiles folded per thread: kFoldPer x kFoldThreads tiles of kTileRed particles
+// cover the largest run (2^24 particles).
+constexpr uint32_t kFoldPer = 16;
+static_assert((unsigned long long)kFoldPer * kFoldThreads * kTileRed >= (1ull << 24), "fold covers 2^24 particles");
+
 __device__ __forceinline__ void fold_sums_body(const RunDev& R)
 {
+    if (R.fused) return;  // this run's scan folds its own tile sums
     RunCtl* ctl = R.ctl;
-    if (ctl->status != 0 || R.fused) return;
-    const bool bad = ctl->bad != 0;
-    const double M = key_value(ctl->maxkey);
-    const bool usable = !bad && ctl->maxkey != 0 && M != -__builtin_huge_val();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t T = R.red_tiles;
     const uint32_t per = (T + kFoldThreads - 1) / kFoldThreads;
     const uint32_t t0 = threadIdx.x * per;
     const uint32_t t1 = t0 + per < T ? t0 + per : T;
     const bool ess = R.ess_t != 0;
+    // every tile sum this thread folds is requested at once, before the
+    // control block is consumed (zeros past the thread's tiles leave the
+    // sums' bits unchanged: they are non-negative)
     double q_local = 0.0, e_local = 0.0;
+#pragma unroll
+    for (uint32_t i = 0; i < kFoldPer; ++i) {
+        const bool mine = i < per && t0 + i < T;
+        q_local += mine ? R.part_q[t0 + i] : 0.0;
+        e_local += mine ? R.part_e[t0 + i] : 0.0;
+    }
+    if (ctl->status != 0) return;
+    const bool bad = ctl->bad != 0;
+    const double M = key_value(ctl->maxkey);
+    const bool usable = !bad && ctl->maxkey != 0 && M != -__builtin_huge_val();
     U128 q2_local{0ull, 0ull};
-    if (usable)
-        for (uint32_t t = t0; t < t1; ++t) {
-            q_local += R.part_q[t];
-            e_local += R.part_e[t];
-            if (ess) q2_local = add128(q2_local, U128{R.part_q2[2 * t + 1], R.part_q2[2 * t]});
-        }
+    if (!usable) {
+        q_local = 0.0;
+        e_local = 0.0;
+    }
+    if (usable) {
+        if (ess)
+            for (uint32_t t = t0; t < t1; ++t) q2_local = add128(q2_local, U128{R.part_q2[2 * t + 1], R.part_q2[2 * t]});
+    }
     const double q_incl = wave_incl_scan<OpAddF64>(q_local);  // exact: integer-valued
     const double e_wave = wave_sum(e_local);
     const U128 q2_wave = ess ? wave_sum(q2_local) : U128{0ull, 0ull};
@@ -1048,10 +1072,17 @@ __device__ __forceinline__ void fold_sums_body(const RunDev& R)
     const bool resample = active && ess_says_resample(R.ess_t, R.n, q_all, q2_all);
     if (usable && resample) {
         double run = q_before + (q_incl - q_local);
-        for (uint32_t t = t0; t < t1; ++t) {
-            R.prefix[t] = run;
-            run += R.part_q[t];
-        }
+        // all of this thread's tile sums in registers first: a load placed
+        // after a store to prefix could not be moved above it
+        double qv[kFoldPer];
+#pragma unroll
+        for (uint32_t i = 0; i < kFoldPer; ++i) qv[i] = (i < per && t0 + i < T) ? R.part_q[t0 + i] : 0.0;
+#pragma unroll
+        for (uint32_t i = 0; i < kFoldPer; ++i)
+            if (i < per && t0 + i < T) {
+                R.prefix[t0 + i] = run;
+                run += qv[i];
+            }
     }
     if (threadIdx.x == 0) {
         ctl->m_cur = M;
@@ -1449,24 +1480,34 @@ __global__ void k_model_setup(ModelDev* m)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_propagate(int kind, int precision, const RunDev* runs, const TileRef* tiles, uint32_t n_tiles,
-                            hipStream_t st)
+template <int Kind, class Real>
+static hipError_t launch_table_sized(int lanes, const RunDev* runs, const TileRef* tiles, uint32_t n_tiles,
+                                     hipStream_t st)
+{
+    if (lanes == 256) hipLaunchKernelGGL((k_propagate<Kind, Real, 256>), dim3(n_tiles), dim3(256), 0, st, runs, tiles);
+    else hipLaunchKernelGGL((k_propagate<Kind, Real, 128>), dim3(n_tiles), dim3(128), 0, st, runs, tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_propagate(int kind, int precision, int lanes, const RunDev* runs, const TileRef* tiles,
+                            uint32_t n_tiles, hipStream_t st)
 {
     if (n_tiles == 0) return hipSuccess;
-    dim3 g(n_tiles), b(prop_threads(kind));
-    if (kind == 0) hipLaunchKernelGGL((k_propagate<0, double>), g, b, 0, st, runs, tiles);
-    else if (kind == 1 && precision == 32) hipLaunchKernelGGL((k_propagate<1, float>), g, b, 0, st, runs, tiles);
-    else if (kind == 1) hipLaunchKernelGGL((k_propagate<1, double>), g, b, 0, st, runs, tiles);
-    else if (kind == 2 && precision == 32) hipLaunchKernelGGL((k_propagate<2, float>), g, b, 0, st, runs, tiles);
-    else if (kind == 2) hipLaunchKernelGGL((k_propagate<2, double>), g, b, 0, st, runs, tiles);
-    else if (kind == 3 && precision == 32) hipLaunchKernelGGL((k_propagate<3, float>), g, b, 0, st, runs, tiles);
-    else if (kind == 3) hipLaunchKernelGGL((k_propagate<3, double>), g, b, 0, st, runs, tiles);
-    else if (kind == 4 && precision == 32) hipLaunchKernelGGL((k_propagate<4, float>), g, b, 0, st, runs, tiles);
-    else if (kind == 4) hipLaunchKernelGGL((k_propagate<4, double>), g, b, 0, st, runs, tiles);
-    else if (kind == 6) hipLaunchKernelGGL((k_propagate<6, double>), g, b, 0, st, runs, tiles);
-    else if (precision == 32) hipLaunchKernelGGL((k_propagate<5, float>), g, b, 0, st, runs, tiles);
-    else hipLaunchKernelGGL((k_propagate<5, double>), g, b, 0, st, runs, tiles);
-    return hipGetLastError();
+    const bool f32 = precision == 32;
+    switch (kind) {
+    case 0: return launch_table_sized<0, double>(lanes, runs, tiles, n_tiles, st);
+    case 1: return f32 ? launch_table_sized<1, float>(lanes, runs, tiles, n_tiles, st)
+                       : launch_table_sized<1, double>(lanes, runs, tiles, n_tiles, st);
+    case 2: return f32 ? launch_table_sized<2, float>(lanes, runs, tiles, n_tiles, st)
+                       : launch_table_sized<2, double>(lanes, runs, tiles, n_tiles, st);
+    case 3: return f32 ? launch_table_sized<3, float>(lanes, runs, tiles, n_tiles, st)
+                       : launch_table_sized<3, double>(lanes, runs, tiles, n_tiles, st);
+    case 4: return f32 ? launch_table_sized<4, float>(lanes, runs, tiles, n_tiles, st)
+                       : launch_table_sized<4, double>(lanes, runs, tiles, n_tiles, st);
+    case 6: return launch_table_sized<6, double>(lanes, runs, tiles, n_tiles, st);
+    default: return f32 ? launch_table_sized<5, float>(lanes, runs, tiles, n_tiles, st)
+                        : launch_table_sized<5, double>(lanes, runs, tiles, n_tiles, st);
+    }
 }
 
 template <int Kind, class Real>

@@ -30,6 +30,7 @@ import sqlite3
 KERNELS = {
     "k_propagate_one<6": "propagate_program",
     "k_propagate": "propagate",
+    "k_maxkey": "maxkey",
     "k_fold_sums": "fold_sums",
     "k_reduce": "reduce",
     "k_scan_anc": "scan_anc",
@@ -132,7 +133,7 @@ def _launch_stats(values):
     med = sorted(values)[len(values) // 2]
     busy = [v for v in values if v >= 0.01 * med]
     return {"launches": len(busy), "idle_launches": len(values) - len(busy),
-            "bytes_per_launch": sum(busy) / len(busy)}
+            "bytes_per_launch": sum(busy) / len(busy), "bytes_total": sum(values)}
 
 
 def traffic(fetch_db: str, write_db: str) -> dict:
@@ -151,7 +152,10 @@ def traffic(fetch_db: str, write_db: str) -> dict:
     for k in result["FETCH_SIZE"]["kernels"]:
         f = result["FETCH_SIZE"]["kernels"][k]["bytes_per_launch"]
         w = result["WRITE_SIZE"]["kernels"].get(k, {}).get("bytes_per_launch", 0.0)
+        total = (result["FETCH_SIZE"]["kernels"][k]["bytes_total"] +
+                 result["WRITE_SIZE"]["kernels"].get(k, {}).get("bytes_total", 0.0))
         kernels[k] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w, "hbm_bytes_per_launch": f + w,
+                      "hbm_bytes_total": total,
                       "launches": result["FETCH_SIZE"]["kernels"][k]["launches"],
                       "idle_launches": result["FETCH_SIZE"]["kernels"][k]["idle_launches"]}
     return {"kernels": kernels,
@@ -179,6 +183,7 @@ def main(argv=None):
     f.add_argument("--cmd-fetch", required=True)
     f.add_argument("--cmd-write", required=True)
     f.add_argument("--source-sha", required=True)
+    f.add_argument("--runs", type=int, default=1, help="complete runs the profiled command made")
     a = ap.parse_args(argv)
     if a.what in ("trace", "counters"):
         title = a.title or a.out.rsplit("/", 1)[-1].rsplit(".", 1)[0]
@@ -188,7 +193,7 @@ def main(argv=None):
         print(text)
     else:
         d = traffic(a.fetch_db, a.write_db)
-        d.update({"source_sha": a.source_sha, "commands": {"fetch": a.cmd_fetch, "write": a.cmd_write},
+        d.update({"source_sha": a.source_sha, "runs": a.runs, "commands": {"fetch": a.cmd_fetch, "write": a.cmd_write},
                   "calibration": f"{CALIBRATION_KERNEL} of {CALIBRATION_BYTES} bytes, largest dispatch"})
         open(a.out, "w").write(json.dumps(d, indent=1) + "\n")
         print(json.dumps(d, indent=1))

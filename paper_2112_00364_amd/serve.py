@@ -102,6 +102,25 @@ def serve_one_at_a_time(ctx: smc.Context, reqs, honour_arrivals=True, log_every=
     return out, time.perf_counter() - t0
 
 
+def fifo_replay(served, reqs):
+    """One-at-a-time FIFO latencies of a stream from measured service times.
+    `served` holds each request served alone back to back (serve_one_at_a_time
+    with honour_arrivals=False: start and done of its plain run on the GPU);
+    with the arrivals now in `reqs`, request i starts at max(arrival_i,
+    done_{i-1}) and takes its measured service time. This is the real-time
+    FIFO replay without the idle waits, so one measured pass serves every
+    arrival rate. Returns (results, makespan)."""
+    service = {r["id"]: (r["done"] - r["start"], r) for r in served}
+    out = []
+    free_at = 0.0
+    for q in sorted(reqs, key=lambda x: x["arrival"]):
+        dt, r = service[q["id"]]
+        start = max(q["arrival"], free_at)
+        free_at = start + dt
+        out.append(dict(r, arrival=q["arrival"], start=start, done=free_at))
+    return out, free_at
+
+
 def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: int = 8,
                   max_live: int = 256, honour_arrivals=True, log_every=100):
     """Continuous batching: admit while memory and slots allow, tick, retire.

@@ -150,6 +150,7 @@ def lib():
         "smc_batch_create": [vp, C.POINTER(vp)],
         "smc_batch_add": [vp, vp, u64, u64, C.POINTER(i32)],
         "smc_batch_tick": [vp, i32],
+        "smc_batch_set_workgroup": [vp, i32, i32],
         "smc_batch_poll": [vp, i32, vp, vp, vp, vp],
         "smc_batch_retire": [vp, i32],
         "smc_batch_destroy": [vp],
@@ -436,6 +437,11 @@ class Batch:
 
     def tick(self, rounds: int = 1):
         _check(lib().smc_batch_tick(self._h, int(rounds)))
+
+    def set_workgroup(self, slot: int, lanes: int):
+        """Lanes per propagation work-group of one run of the batch (128 or 256;
+        results unchanged)."""
+        _check(lib().smc_batch_set_workgroup(self._h, int(slot), int(lanes)))
 
     def poll(self):
         k = self.n_slots

@@ -23,21 +23,30 @@ def test_algorithmic_bytes_per_round():
     assert run_total == pytest.approx(n * (17 + 30 * (rounds - 1)), rel=1e-12)
     assert bench.bytes_per_launch("reduce", n, rounds) == n * 8 + (n // 1024) * 16
     assert bench.bytes_per_launch("scan_anc", n, rounds) * rounds == pytest.approx(n * 12 * (rounds - 1), rel=1e-12)
-    # the headline launch figure quoted with the roofline: 31.4 MB per propagation launch
+    # the headline figure quoted with the roofline: 31.4 MB per propagation step
     assert bench.bytes_per_launch("propagate", n, rounds) == pytest.approx(31.43e6, rel=1e-3)
+    # single-pass resampling reads lw 8 and writes anc 4, except in the final round
+    assert bench.bytes_per_launch("resample", n, rounds) * rounds == pytest.approx(n * (8 * rounds + 4 * (rounds - 1)),
+                                                                                  rel=1e-12)
+    # a split propagation's two launches make one step
+    assert bench.STEPS["propagate"] == ("propagate", "hidden")
 
 
 def test_traffic_record_only_for_current_kernels(tmp_path, monkeypatch):
+    """Traffic per round of a step: every dispatch of the step's kernels in the
+    profiled runs, over runs x rounds; only while the record's kernel sources
+    are the current ones."""
     os.makedirs(tmp_path / "profiles")
-    rec = {"kernels": {"propagate": {"hbm_bytes_per_launch": 123.0}}, "source_sha": "aaaa"}
+    rec = {"kernels": {"propagate": {"hbm_bytes_total": 1000.0}, "hidden": {"hbm_bytes_total": 230.0}},
+           "source_sha": "aaaa", "runs": 2}
     (tmp_path / "profiles" / "t.json").write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "aaaa")
-    assert bench.measured_traffic("propagate", 1.0, "t.json") == 123.0
-    assert bench.measured_traffic("reduce", 1.0, "t.json") is None      # kernel not in the record
-    assert bench.measured_traffic("propagate", 1.0, "none.json") is None  # no record
+    assert bench.measured_traffic("propagate", 5, "t.json") == pytest.approx(1230.0 / 10)
+    assert bench.measured_traffic("reduce", 5, "t.json") is None      # kernel not in the record
+    assert bench.measured_traffic("propagate", 5, "none.json") is None  # no record
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "bbbb")
-    assert bench.measured_traffic("propagate", 1.0, "t.json") is None   # kernels changed since
+    assert bench.measured_traffic("propagate", 5, "t.json") is None   # kernels changed since
 
 
 def test_kernel_source_hash_ignores_host_engine():

@@ -337,55 +337,6 @@ def test_batch_matches_runs_alone(smc, oracle, ctx):
         m.close()
 
 
-# --- full size (2^20 particles, 256 tips): sampled checks --------------------------------
-
-def test_crbd_full_size_sampled(smc, oracle, ctx):
-    """The headline configuration: every checked round's ancestors recomputed by
-    the oracle from the GPU's own log-weights (bit-exact), and sampled particles'
-    propagation recomputed one by one from their gathered state."""
-    n = 1 << 20
-    tree = I.yule_tree(256, 3000)
-    spec = I.crbd_spec(tree, precision=32)
-    model = smc.Model(ctx, spec)
-    gpu = smc.Run(model, n, 1)
-    rng = np.random.default_rng(5)
-    checked = {0, 1, 2, 37, 128, 300, 509}
-    logz = 0.0
-    rnd = 0
-    say("crbd full size", n)
-    while True:
-        if rnd in checked and rnd > 0:
-            blk_in = gpu.blk()
-            lam_in = gpu.field(0, np.float32)
-            mu_in = gpu.field(1, np.float32)
-        gpu.step()
-        if rnd in checked:
-            lw = gpu.lw()
-            if rnd > 0:
-                lam_out, mu_out, blk_out = gpu.field(0, np.float32), gpu.field(1, np.float32), gpu.blk()
-                for j in rng.integers(0, n, size=48):
-                    b, l, r, _, _ = oracle.propagate_particle(
-                        spec, 1, int(j), rnd, blk_in[j], [float(lam_in[j]), float(mu_in[j])], [rnd])
-                    assert b == blk_out[j]
-                    assert bits([l])[0] == bits([lw[j]])[0], (rnd, j, l, lw[j])
-                    assert np.float32(r[0]) == lam_out[j] and np.float32(r[1]) == mu_out[j]
-            st_ref, anc_ref, inc_ref, _ = oracle.systematic(lw, 1, rnd)
-        gpu.resample()
-        done, st = gpu.done() if rnd in checked or rnd >= 509 else (False, 0)
-        if rnd in checked and st == smc.OK:
-            assert np.array_equal(gpu.anc(), anc_ref), rnd
-        if done:
-            break
-        rnd += 1
-        assert rnd < 600
-    s = gpu.stats()
-    assert s["status"] == smc.FINISHED and s["round"] == 510
-    assert s["block_steps"] == n * 511
-    assert math.isfinite(s["log_z"])
-    gpu.close()
-    model.close()
-
-
 def test_graph_replays_match_eager_runs(smc, oracle, ctx):
     """run_to_end replays one captured graph; each replay after a reset (with
     eager runs and synchronisations in between) equals an eager run and the

@@ -38,3 +38,38 @@ def test_rescaled_arrivals_rate():
     S.rescale_arrivals(reqs, 50.0, 2)
     t = np.array([r["arrival"] for r in reqs])
     assert abs(len(t) / t[-1] - 50.0) < 3.0
+
+
+def test_launch_cache_keys_and_round_trip(tmp_path):
+    """Run shapes are keyed by kind, precision and the powers of two above the
+    particle count and tree size; the cache file round-trips."""
+    from paper_2112_00364_amd import autotune as A
+    assert A.shape_key("clads", 32, 4096, 100) == "clads/fp32/n4096/tips128"
+    assert A.shape_key("crbd", 64, 1000, 20) == "crbd/fp64/n1024/tips32"
+    assert A.shape_key("lgssm", 32, 65536, 0) == "lgssm/fp32/n65536/tips0"
+    c = A.LaunchCache(str(tmp_path / "sub" / "launch.json"))
+    assert c.get("x") is None
+    c.put("x", {"lanes": 256, "ms": {"lanes128": 2.0, "lanes256": 1.0}})
+    d = A.LaunchCache(str(tmp_path / "sub" / "launch.json"))
+    assert d.get("x")["lanes"] == 256
+    (tmp_path / "bad.json").write_text("{not json")
+    assert A.LaunchCache(str(tmp_path / "bad.json")).entries == {}
+
+
+def test_fifo_replay_queues_measured_service_times():
+    """One-at-a-time FIFO from measured service times: a request starts when it
+    has arrived and the previous one is done, and takes its own service time."""
+    from paper_2112_00364_amd import serve as S
+    served = [{"id": 0, "start": 0.0, "done": 2.0, "log_z": -1.0, "status": 1, "block_steps": 10},
+              {"id": 1, "start": 2.0, "done": 2.5, "log_z": -2.0, "status": 1, "block_steps": 20},
+              {"id": 2, "start": 2.5, "done": 5.5, "log_z": -3.0, "status": 1, "block_steps": 30}]
+    reqs = [{"id": 0, "arrival": 1.0}, {"id": 1, "arrival": 1.5}, {"id": 2, "arrival": 10.0}]
+    out, makespan = S.fifo_replay(served, reqs)
+    by = {r["id"]: r for r in out}
+    assert (by[0]["start"], by[0]["done"]) == (1.0, 3.0)      # idle server: starts on arrival
+    assert (by[1]["start"], by[1]["done"]) == (3.0, 3.5)      # queued behind request 0
+    assert (by[2]["start"], by[2]["done"]) == (10.0, 13.0)    # server idle again
+    assert makespan == 13.0
+    assert by[1]["log_z"] == -2.0 and by[2]["block_steps"] == 30
+    lat = S.summarize(out, makespan)
+    assert lat["requests"] == 3 and lat["failed"] == 0
