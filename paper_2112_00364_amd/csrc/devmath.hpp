@@ -248,7 +248,9 @@ __device__ inline int draw_poisson(Stream& s, double m)
     if (!(m >= 0.0) || m > fn::kEventCap) return -1;
     if (m == 0.0) return 0;
     const int chunks = (int)__builtin_ceil(m / 32.0);
-    const double mc = m / (double)chunks;
+    // a division by 1 is exact: with one chunk (m <= 32, nearly every draw)
+    // the FP64 division is skipped
+    const double mc = chunks == 1 ? m : m / (double)chunks;
     const double p0 = fn::exp(-mc);
     int total = 0;
     for (int c = 0; c < chunks; ++c) {
