@@ -182,15 +182,26 @@ def batched_clads_cpu(runs_per_worker: int = 8, n: int = 4096, max_workers: int 
             "finished_runs": sum(1 for ok, _ in res if ok)}
 
 
-def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers, alone_path=None, save_alone=None):
+def serving_contexts(smc, ctx):
+    """The per-kind server's contexts: one per model kind, each on its own HIP
+    stream (default priority), and an idle one on which models are registered."""
+    import torch
+    kinds = {k: smc.Context(ctx.device, stream=torch.cuda.Stream(device=ctx.device)) for k in ("crbd", "clads")}
+    return kinds, smc.Context(ctx.device, stream=torch.cuda.Stream(device=ctx.device))
+
+
+def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers, alone_path=None, save_alone=None,
+            mode: str = "single"):
     """Serving stream: every request served alone once, back to back (plain
     runs, FIFO), which gives its service time, its log Z and the
     one-at-a-time service rate; then for each multiplier m the same requests
     arrive (Poisson) at m x that rate and are served (a) one at a time, FIFO:
     latencies from the measured service times, and (b) by continuous
-    batching, in real time. The back-to-back pass can be saved to a JSON file
-    (save_alone) and read back (alone_path), so that the arrival rates of one
-    stream can be measured in separate processes against one pass."""
+    batching, in real time: one batch for all requests (mode "single") or one
+    batch per model kind, each on its own stream (mode "by-kind"). The
+    back-to-back pass can be saved to a JSON file (save_alone) and read back
+    (alone_path), so that the arrival rates of one stream can be measured in
+    separate processes against one pass."""
     from paper_2112_00364_amd import serve as S
     reqs = S.make_requests(n_requests, 5000, rate_per_s=1.0)
     if alone_path:
@@ -205,13 +216,18 @@ def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers, alone_pat
     rate = len(reqs) / t_alone
     out = {"requests": n_requests, "one_at_a_time_service_rate_per_s": rate, "memory_budget_bytes": budget_bytes,
            "one_at_a_time_latencies": "FIFO over the measured service times of the back-to-back pass",
-           "one_at_a_time_pass": alone_path or "measured in this process", "by_arrival_rate": []}
+           "one_at_a_time_pass": alone_path or "measured in this process", "batched_mode": mode,
+           "by_arrival_rate": []}
+    by_kind = serving_contexts(smc, ctx) if mode == "by-kind" else None
     for m in multipliers:
         arr = m * rate
         S.rescale_arrivals(reqs, arr, 5001)
         print(f"serving: one-at-a-time rate {rate:.2f}/s, arrivals at {arr:.2f}/s", file=sys.stderr, flush=True)
         base, t_base = S.fifo_replay(alone, reqs)
-        bat, t_bat = S.serve_batched(ctx, reqs, budget_bytes)
+        if by_kind:
+            bat, t_bat = S.serve_batched_by_kind(by_kind[0], by_kind[1], reqs, budget_bytes)
+        else:
+            bat, t_bat = S.serve_batched(ctx, reqs, budget_bytes)
         same = {r["id"]: r["log_z"] for r in base}
         worst = max(abs(r["log_z"] - same[r["id"]]) / max(1.0, abs(same[r["id"]])) for r in bat)
         identical = all(r["log_z"] == same[r["id"]] for r in bat)
@@ -220,6 +236,9 @@ def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers, alone_pat
                                        "batched": S.summarize(bat, t_bat),
                                        "max_rel_logz_diff_batched_vs_alone": worst,
                                        "identical_log_z_batched_vs_alone": identical})
+    if by_kind:
+        for c in list(by_kind[0].values()) + [by_kind[1]]:
+            c.close()
     return out
 
 
@@ -712,6 +731,8 @@ def main():
     ap.add_argument("--no-tail-call", action="store_true",
                     help="compiled-program point: skip the tail-call form (profiles of the stack-growing form)")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serving-mode", choices=["single", "by-kind"], default="single",
+                    help="serving leg: one batch for all requests, or one batch per model kind on its own stream")
     ap.add_argument("--serving-alone-out", default=None,
                     help="serving leg: write the back-to-back one-at-a-time pass to this JSON file")
     ap.add_argument("--serving-alone-in", default=None,
@@ -758,7 +779,8 @@ def main():
                 "small": lambda: small_crbd_point(smc, ctx, I, cpu=not args.no_cpu_baseline),
                 "batched": lambda: batched_clads(ctx, smc, I, tune=not args.no_autotune),
                 "serving": lambda: serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30),
-                                           rates, args.serving_alone_in, args.serving_alone_out)}
+                                           rates, args.serving_alone_in, args.serving_alone_out,
+                                           args.serving_mode)}
         print(f"{args.only} leg alone", file=sys.stderr, flush=True)
         print(json.dumps({"leg": args.only, args.only: legs[args.only]()}), flush=True)
         return
@@ -867,7 +889,7 @@ def main():
         print("serving leg", file=sys.stderr, flush=True)
         rates = [float(x) for x in args.serving_rates.split(",") if x]
         out["serving"] = serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30), rates,
-                                 args.serving_alone_in, args.serving_alone_out)
+                                 args.serving_alone_in, args.serving_alone_out, args.serving_mode)
     if not args.no_cpu_baseline:
         print("cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_particles)

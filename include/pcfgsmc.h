@@ -367,7 +367,10 @@ smc_status smc_resample_weights_noalloc(smc_ctx* ctx, const double* lw, uint64_t
  * counts share the launches and finished runs drop out at once. Results are
  * identical to the same runs executed alone. */
 smc_status smc_batch_create(smc_ctx* ctx, smc_batch** out);
-/* Add a run (Algorithm 1 step 1 for it); *slot receives its index. */
+/* Add a run (Algorithm 1 step 1 for it); *slot receives its index. The model
+ * may be registered on another context of the same device (registration
+ * synchronises its own stream, so a server can register on an idle context
+ * while the batch's stream is busy). */
 smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n_particles, uint64_t seed, int32_t* slot);
 /* Advance every live run by up to `rounds` rounds (step + resample each).
  * From the second tick with the same runs and round count on, the tick's

@@ -333,9 +333,11 @@ void set_prop_tiles(RunDev& h, int lanes)
     h.fused = h.red_tiles <= kMaxFusedRedTiles ? 1u : 0u;
 }
 
-smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r)
+// The run's memory comes from ctx's allocator and its work goes to ctx's
+// stream (a batch's runs use the batch's context, whatever context the model
+// was registered on).
+smc_status build_run(smc_model* m, uint64_t n, uint64_t seed, smc_run* r, smc_ctx* ctx)
 {
-    smc_ctx* ctx = m->ctx;
     r->ctx = ctx;
     r->model = m;
     r->n = n;
@@ -641,7 +643,7 @@ smc_status smc_init(smc_model* model, uint64_t n, uint64_t seed, smc_run** out)
     if (n == 0 || n > kMaxParticles) return fail(SMC_ERR_INVALID, "particle count must be in [1, 2^24]");
     smc_run* r = new (std::nothrow) smc_run();
     if (!r) return fail(SMC_ERR_OOM, "host allocation failed");
-    smc_status s = build_run(model, n, seed, r);
+    smc_status s = build_run(model, n, seed, r, model->ctx);
     if (s != SMC_OK) {
         delete r;
         return s;
@@ -1236,10 +1238,17 @@ smc_status smc_batch_create(smc_ctx* ctx, smc_batch** out)
 smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n, uint64_t seed, int32_t* slot)
 {
     if (!b || !model || !slot) return fail(SMC_ERR_INVALID, "NULL argument");
-    if (model->ctx != b->ctx) return fail(SMC_ERR_INVALID, "model belongs to another context");
-    smc_run* r = nullptr;
-    smc_status s = smc_init(model, n, seed, &r);
-    if (s != SMC_OK) return s;
+    // a model registered on another context of the same device will do (its
+    // registration has completed; its memory is the device's)
+    if (model->ctx->device != b->ctx->device) return fail(SMC_ERR_INVALID, "model belongs to another device");
+    if (n == 0 || n > kMaxParticles) return fail(SMC_ERR_INVALID, "particle count must be in [1, 2^24]");
+    smc_run* r = new (std::nothrow) smc_run();
+    if (!r) return fail(SMC_ERR_OOM, "host allocation failed");
+    const smc_status s = build_run(model, n, seed, r, b->ctx);
+    if (s != SMC_OK) {
+        delete r;
+        return s;
+    }
     int32_t idx = -1;
     for (size_t i = 0; i < b->slots.size(); ++i)
         if (!b->slots[i]) {

@@ -178,6 +178,84 @@ def serve_batched(ctx: smc.Context, reqs, memory_budget: int, rounds_per_tick: i
     return out, time.perf_counter() - t0
 
 
+def serve_batched_by_kind(ctxs: dict, reg_ctx, reqs, memory_budget: int, rounds_per_tick: int = 8,
+                          max_live: int = 256, honour_arrivals=True, log_every=100):
+    """Continuous batching with one batch per model kind, each on its own
+    context (its own HIP stream): a tick of one batch does not wait for the
+    other's, so requests of a light model are not held by a heavy one's long
+    chains. A batch is ticked again as soon as its previous tick has finished
+    (an event on its stream, queried without blocking); admission as in
+    serve_batched, against one memory budget for both. ctxs maps a request kind
+    to the Context its batch runs on; models are registered on reg_ctx, whose
+    stream stays idle, so an admission never waits for a running tick."""
+    import torch
+    pending = collections.deque(sorted(reqs, key=lambda r: r["arrival"]))
+    kinds = sorted(ctxs)
+    batches = {k: smc.Batch(ctxs[k]) for k in kinds}
+    live = {k: {} for k in kinds}      # kind -> slot -> (request, model, admitted time)
+    in_flight = {k: None for k in kinds}  # kind -> event recorded after its last tick
+    used = 0
+    out = []
+    t0 = time.perf_counter()
+    while pending or any(live[k] for k in kinds):
+        now = time.perf_counter() - t0
+        n_live = sum(len(live[k]) for k in kinds)
+        while pending and (not honour_arrivals or pending[0]["arrival"] <= now):
+            r = pending[0]
+            if n_live and (used + r["bytes"] > memory_budget or n_live >= max_live):
+                break
+            k = r["kind"]
+            model = None
+            try:
+                model = smc.Model(reg_ctx, r["spec"])
+                slot = batches[k].add(model, r["n"], r["seed"])
+            except smc.SMCError as e:
+                if model is not None:
+                    model.close()
+                if e.code != smc.ERR_OOM or not n_live:
+                    raise
+                break
+            pending.popleft()
+            live[k][slot] = (r, model, time.perf_counter() - t0)
+            used += r["bytes"]
+            n_live += 1
+        progressed = False
+        for k in kinds:
+            ev = in_flight[k]
+            if ev is not None:
+                if not ev.query():
+                    continue
+                in_flight[k] = None
+                done, lz, st, steps = batches[k].poll()
+                now = time.perf_counter() - t0
+                for slot in list(live[k]):
+                    if done[slot]:
+                        r, model, admitted = live[k].pop(slot)
+                        out.append({"id": r["id"], "arrival": r["arrival"], "start": admitted, "done": now,
+                                    "log_z": float(lz[slot]), "status": int(st[slot]),
+                                    "block_steps": int(steps[slot])})
+                        batches[k].retire(slot)
+                        model.close()
+                        used -= r["bytes"]
+                        if log_every and len(out) % log_every == 0:
+                            _progress(f"batched by kind: {len(out)}/{len(reqs)} done at {now:.1f} s")
+                progressed = True
+            if live[k] and in_flight[k] is None:
+                batches[k].tick(rounds_per_tick)
+                ev = torch.cuda.Event()
+                ev.record(ctxs[k].stream)
+                in_flight[k] = ev
+                progressed = True
+        if not progressed:
+            if not any(live[k] for k in kinds) and pending:
+                time.sleep(max(0.0, pending[0]["arrival"] - (time.perf_counter() - t0)))
+            else:
+                time.sleep(0.0002)
+    for k in kinds:
+        batches[k].close()
+    return out, time.perf_counter() - t0
+
+
 def summarize(results, makespan: float) -> dict:
     lat = np.array([r["done"] - r["arrival"] for r in results])
     steps = sum(r["block_steps"] for r in results)

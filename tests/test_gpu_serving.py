@@ -104,3 +104,87 @@ def test_batch_tick_graph_replays_match_runs_alone(ctx):
     for s, want in zip(slots, alone):
         assert lz[s] == want, (s, lz[s], want)
     b.close()
+
+
+def test_batch_with_a_run_above_2p20_particles(ctx, oracle):
+    """A run of more than 2^20 particles (its tile sums folded by the separate
+    one-work-group kernel, inside the batch's fold launch) advanced together
+    with small runs of other kinds: every run's log Z, status and block steps
+    as on the oracle."""
+    from paper_2112_00364_amd import smc
+    specs = [I.lgssm_spec(I.lgssm_data(6, 31), 32), I.crbd_spec(I.yule_tree(14, 5), precision=32),
+             I.clads_spec(I.yule_tree(12, 6), precision=32), I.geometric_spec(True)]
+    ns = [(1 << 20) + 4097, 3000, 2048, 700]
+    models = [smc.Model(ctx, s) for s in specs]
+    b = smc.Batch(ctx)
+    try:
+        slots = [b.add(m, n, 900 + i) for i, (m, n) in enumerate(zip(models, ns))]
+        for _ in range(300):
+            b.tick(4)
+            done, lz, st, steps = b.poll()
+            if done.all():
+                break
+        assert done.all()
+        for i, (s, n) in enumerate(zip(specs, ns)):
+            ref = oracle.Run(s, n, 900 + i)
+            ref.run_to_end()
+            assert st[slots[i]] == ref.status
+            assert int(steps[slots[i]]) == ref.block_steps
+            assert abs(lz[slots[i]] - ref.log_z) <= 1e-9 * abs(ref.log_z), (i, lz[slots[i]], ref.log_z)
+    finally:
+        b.close()
+        for m in models:
+            m.close()
+
+
+def test_served_results_equal_alone_at_larger_particle_counts(ctx):
+    """The serving stream's larger requests (up to 2^16 particles here; the
+    stream goes to 2^18): admitted into a running batch they end exactly as
+    alone (log Z bits, status, block steps)."""
+    from paper_2112_00364_amd import serve as S
+    from paper_2112_00364_amd import smc
+    reqs = S.make_requests(12, 78, rate_per_s=200.0)
+    for r in reqs:
+        r["n"] = min(r["n"], 1 << 16)
+        r["bytes"] = S.footprint_bytes(r["kind"], r["n"], 32, r["depth"])
+    budget = 3 * max(r["bytes"] for r in reqs)
+    bat, _ = S.serve_batched(ctx, reqs, budget, rounds_per_tick=8)
+    alone, _ = S.serve_one_at_a_time(ctx, reqs, honour_arrivals=False)
+    a = {r["id"]: r for r in alone}
+    assert len(bat) == len(reqs) and max(r["n"] for r in reqs) > 2048
+    for r in bat:
+        assert r["status"] == a[r["id"]]["status"]
+        assert r["log_z"] == a[r["id"]]["log_z"]
+        assert r["block_steps"] == a[r["id"]]["block_steps"]
+
+
+def test_served_by_kind_results_equal_alone(ctx, oracle):
+    """One batch per model kind, each on its own stream, with models registered
+    on a third context: every request ends exactly as alone (log Z bits,
+    status, block steps), and the small ones as on the oracle."""
+    import torch
+    from paper_2112_00364_amd import serve as S
+    from paper_2112_00364_amd import smc
+    reqs = S.make_requests(24, 79, rate_per_s=200.0)
+    for r in reqs:
+        r["n"] = min(r["n"], 4096)
+        r["bytes"] = S.footprint_bytes(r["kind"], r["n"], 32, r["depth"])
+    ctxs = {k: smc.Context(0, stream=torch.cuda.Stream(device=0)) for k in ("crbd", "clads")}
+    reg = smc.Context(0, stream=torch.cuda.Stream(device=0))
+    try:
+        budget = 4 * max(r["bytes"] for r in reqs)
+        bat, _ = S.serve_batched_by_kind(ctxs, reg, reqs, budget, rounds_per_tick=5)
+    finally:
+        for c in list(ctxs.values()) + [reg]:
+            c.close()
+    alone, _ = S.serve_one_at_a_time(ctx, reqs, honour_arrivals=False)
+    a = {r["id"]: r for r in alone}
+    assert len(bat) == len(reqs) and {r["kind"] for r in reqs} == {"crbd", "clads"}
+    for r in bat:
+        assert r["status"] == a[r["id"]]["status"] == smc.FINISHED
+        assert r["log_z"] == a[r["id"]]["log_z"]
+        assert r["block_steps"] == a[r["id"]]["block_steps"]
+    for req in reqs[:4]:
+        ref = oracle.Run(req["spec"], req["n"], req["seed"])
+        ref.run_to_end()
+        assert abs(a[req["id"]]["log_z"] - ref.log_z) <= 1e-9 * abs(ref.log_z)
