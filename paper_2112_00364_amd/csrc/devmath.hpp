@@ -21,6 +21,17 @@ struct Words4 {
     uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ c; on the device one three-input bit operation (truth table 0x96)
+// in place of two xors.
+__host__ __device__ inline uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+#else
+    return a ^ b ^ c;
+#endif
+}
+
 __host__ __device__ inline Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                             uint32_t k0, uint32_t k1)
 {
@@ -30,8 +41,8 @@ __host__ __device__ inline Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kMulA * c0;
         const uint64_t pb = (uint64_t)kMulB * c2;
-        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(pa >> 32), c3, k1);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
@@ -95,6 +106,24 @@ constexpr double kLog2e = 1.442695040888963407359924681001892137427;
 constexpr double kRoot2 = 1.41421356237309504880168872420969807857;
 constexpr double kTau = 6.283185307179586476925286766559005768394;   // 2 pi
 
+// a / b correctly rounded, for operands kept in range by the caller: 2^-900 <
+// |b| < 2^900, and a = 0 or 2^-900 < |a| < 2^900, with a normal quotient. The
+// reciprocal estimate is refined by two Newton steps and the quotient corrected
+// once with its exact residual: the steps of the compiler's IEEE division,
+// without the operand scaling and special-case fix-up that this range never
+// takes (three instructions fewer, same bits).
+__device__ inline double div_in_range(double a, double b)
+{
+    double y = __builtin_amdgcn_rcp(b);
+    double e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-b, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    const double q = a * y;
+    const double r = __builtin_fma(-b, q, a);
+    return __builtin_fma(r, y, q);
+}
+
 __device__ inline double two_to(int n)   // 2^n, -1022 <= n <= 1023
 {
     return __longlong_as_double((long long)(n + 1023) << 52);
@@ -150,7 +179,7 @@ __device__ inline double log(double x)
         k += 1;
     }
     const double f = m - 1.0;
-    const double s = f / (2.0 + f);
+    const double s = div_in_range(f, 2.0 + f);  // |f| < 0.42, 2 + f in [1.7, 2.5)
     const double z = s * s;
     double R = 1.0 / 21.0;
     R = __builtin_fma(R, z, 1.0 / 19.0);
@@ -260,7 +289,9 @@ __device__ inline int draw_poisson(Stream& s, double m)
         int k = 0;
         while (u > F && k < fn::kMaxInversionSteps) {
             k += 1;
-            p = p * mc / (double)k;
+            // p * mc stays above 2^-80 before the inverted CDF passes u (mc <= 32,
+            // u <= 1 - 2^-33) and 1 <= k <= 10^4: inside div_in_range's range
+            p = fn::div_in_range(p * mc, (double)k);
             F = F + p;
         }
         total += k;
