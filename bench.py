@@ -98,6 +98,26 @@ def cpu_baseline(spec, n: int):
                       f"single thread, {dt:.1f} s"}
 
 
+def clads_run_bytes(tree, n: int) -> float:
+    """Algorithmic HBM bytes of one complete ClaDS run of n particles (FP32
+    state). Round 0 writes block 1 + state 16 + stack level 0 4 + lw 8. A
+    branch round at node r with sp pending rates below it: anc 4 + gathered
+    block 1 + state 16 + the sp live stack levels 4 sp read; block 1 + state 16
+    + the carried levels 4 sp (+ the new level 4 at an internal node) + lw 8
+    written. Every round but the last resamples: lw 8 read twice, anc 4
+    written (the reduction's tile sums aside)."""
+    left = tree["left"]
+    total = 29.0
+    cur = 1
+    for node in range(1, len(left)):
+        internal = left[node] >= 0
+        total += 46 + 8 * cur + (4 if internal else 0)
+        cur = cur + 1 if internal else max(cur - 1, 0)
+    rounds = len(left)
+    total += 20.0 * (rounds - 1) + 8.0
+    return n * total
+
+
 def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16, tune=True, cache_path=None):
     """512 independent ClaDS runs (trees of 32-128 tips, seeds 4000 + r), 4096
     particles each, advanced together by the batch API. Before the timed
@@ -108,7 +128,9 @@ def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16, tune=True, 
     from paper_2112_00364_amd import autotune as A
     rng = np.random.default_rng(4000)
     tips = rng.integers(32, 129, size=runs)
-    models = [smc.Model(ctx, I.clads_spec(I.yule_tree(int(t), 4000 + r), precision=32)) for r, t in enumerate(tips)]
+    trees = [I.yule_tree(int(t), 4000 + r) for r, t in enumerate(tips)]
+    models = [smc.Model(ctx, I.clads_spec(tr, precision=32)) for tr in trees]
+    alg_bytes = sum(clads_run_bytes(tr, n) for tr in trees)
     lanes = {}
     tune_s = 0.0
     cache = A.LaunchCache(cache_path)
@@ -146,7 +168,12 @@ def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16, tune=True, 
             "tips": [int(tips.min()), int(tips.max())], "seconds": dt, "block_steps": total,
             "block_steps_per_s": total / dt, "finished_runs": ok, "rounds_per_tick": rounds_per_tick,
             "workgroup_lanes": lanes, "autotune": {key: cache.get(key) for key in lanes},
-            "autotune_seconds": tune_s}
+            "autotune_seconds": tune_s,
+            # the whole leg (every launch of every tick) against HBM: the batch is bound by its
+            # longest dependent chains, not by memory
+            "roofline": {"bound": "hbm", "achieved": round(alg_bytes / dt / 1e9, 3), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg_bytes / dt / 1e9 / HBM_PEAK_GBS, 6), "traffic": None,
+                         "kernel": "all launches of the leg", "alg_bytes": alg_bytes}}
 
 
 def _clads_oracle_run(job):
@@ -291,10 +318,16 @@ def seir_point(smc, ctx, I, n: int = 1 << 18, days: int = 100, runs: int = 3, cp
     ms = start.elapsed_time(end) / runs
     s = run.stats()
     run.close()
+    # per particle and round, FP32 state (6 reals, 9 counts: 60 B): anc 4 + gathered block 1 +
+    # gathered state 60 read, block 1 + state 60 + lw 8 written (round 0 writes only: 69);
+    # resampling as in every model
+    byte_model = {"propagate": lambda R: n * (69 + 134 * (R - 1)) / R,
+                  "reduce": n * 8.0 + n / 1024 * 16, "scan_anc": lambda R: n * 12.0 * (R - 1) / R}
+    kernels, roofline = profile_steps(smc, model, n, 4343, ms, byte_model)
     model.close()
     out = {"workload": f"seir_synthetic{days}d_n{n}", "particles": n, "days": days, "runs": runs,
            "ms_per_run": ms, "status": s["status"], "log_z_last": s["log_z"],
-           "block_steps_per_s": s["block_steps"] / (ms / 1e3)}
+           "block_steps_per_s": s["block_steps"] / (ms / 1e3), "roofline": roofline, "kernels": kernels}
     if cpu:
         from oracle import oracle as O
         m = 1 << 12
@@ -544,7 +577,8 @@ def profile_steps(smc, model, n: int, seed: int, ms_per_run: float, byte_model: 
     run - timed time per run) / launches and taken off every launch (the raw
     figures are kept beside). Returns the per-launch table, the per-step table
     (a split propagation is two launches per round) and the roofline of the
-    dominant step; byte_model maps a step to its algorithmic bytes per round."""
+    dominant step; byte_model maps a step to its algorithmic bytes per round
+    (a number, or a function of the run's round count)."""
     prof = smc.Run(model, n, seed)
     prof.profile(True)
     prof.run_to_end()
@@ -570,6 +604,7 @@ def profile_steps(smc, model, n: int, seed: int, ms_per_run: float, byte_model: 
         entry = {"kernels": [p for p in parts if p in kernels], "avg_us_per_round": avg_us, "rounds": rounds_run}
         if step in byte_model:
             b = byte_model[step]
+            b = b(rounds_run) if callable(b) else b
             entry.update({"alg_bytes_per_round": b, "achieved_GBs": b / (avg_us * 1e-6) / 1e9})
         steps[step] = entry
     dom = max((k for k in steps if "achieved_GBs" in steps[k]),

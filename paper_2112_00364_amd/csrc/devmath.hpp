@@ -106,6 +106,30 @@ constexpr double kLog2e = 1.442695040888963407359924681001892137427;
 constexpr double kRoot2 = 1.41421356237309504880168872420969807857;
 constexpr double kTau = 6.283185307179586476925286766559005768394;   // 2 pi
 
+// a * b + c rounded once, with the constant c read from scalar registers: the
+// compiler's own form of a polynomial step first copies c into the vector
+// registers it accumulates in (two extra vector moves per step). Same operation
+// and rounding as __builtin_fma.
+__device__ inline double fma_sc(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+
+// One polynomial step. kScalarCoef: the coefficient is read from scalar
+// registers (fma_sc), which keeps it out of the vector register file and the
+// vector instruction stream - the better placement where many wavefronts share
+// each SIMD. Otherwise the compiler places it (vector registers, hoisted where
+// registers allow), which is faster for a lone long chain of dependent steps
+// with little else resident. Same value either way.
+template <bool kScalarCoef>
+__device__ inline double coef_fma(double a, double b, double c)
+{
+    if constexpr (kScalarCoef) return fma_sc(a, b, c);
+    else return __builtin_fma(a, b, c);
+}
+
 // a / b correctly rounded, for operands kept in range by the caller: 2^-900 <
 // |b| < 2^900, and a = 0 or 2^-900 < |a| < 2^900, with a normal quotient. The
 // reciprocal estimate is refined by two Newton steps and the quotient corrected
@@ -133,6 +157,7 @@ __device__ inline double two_to(int n)   // 2^n, -1022 <= n <= 1023
 // (head, tail); e^r from its degree-13 Taylor polynomial (Horner, fma);
 // result scaled by 2^n. Below -708 the result is flushed to +0, above 709 it
 // is +inf.
+template <bool kSc = true>
 __device__ inline double exp(double x)
 {
     if (x != x) return x;
@@ -141,16 +166,16 @@ __device__ inline double exp(double x)
     const double n = __builtin_rint(x * kLog2e);
     const double r = (x - n * kLn2Head) - n * kLn2Tail;
     double p = 1.0 / 6227020800.0;
-    p = __builtin_fma(p, r, 1.0 / 479001600.0);
-    p = __builtin_fma(p, r, 1.0 / 39916800.0);
-    p = __builtin_fma(p, r, 1.0 / 3628800.0);
-    p = __builtin_fma(p, r, 1.0 / 362880.0);
-    p = __builtin_fma(p, r, 1.0 / 40320.0);
-    p = __builtin_fma(p, r, 1.0 / 5040.0);
-    p = __builtin_fma(p, r, 1.0 / 720.0);
-    p = __builtin_fma(p, r, 1.0 / 120.0);
-    p = __builtin_fma(p, r, 1.0 / 24.0);
-    p = __builtin_fma(p, r, 1.0 / 6.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 479001600.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 39916800.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 3628800.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 362880.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 40320.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 5040.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 720.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 120.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 24.0);
+    p = coef_fma<kSc>(p, r, 1.0 / 6.0);
     p = __builtin_fma(p, r, 0.5);
     p = __builtin_fma(p, r, 1.0);
     p = __builtin_fma(p, r, 1.0);
@@ -160,15 +185,18 @@ __device__ inline double exp(double x)
 // log: x = 2^k m, m in [sqrt(2)/2, sqrt(2)); with f = m - 1 and s = f / (2 + f),
 // log m = 2 atanh s = 2s + 2s * z * R(z), z = s^2, R(z) = sum_{j<10} z^j / (2j + 3);
 // log x = k ln2_head + (k ln2_tail + log m).
+template <bool kSc = true>
 __device__ inline double log(double x)
 {
-    if (x != x) return x;
-    if (x < 0.0) return __builtin_nan("");
-    if (x == 0.0) return -__builtin_huge_val();
-    if (x == __builtin_huge_val()) return x;
     int k = 0;
-    if (x < 0x1p-1022) {
-        x = x * 0x1p54;
+    // one class test (positive normal: mask bit 8) keeps the special cases off
+    // the common path
+    if (!__builtin_amdgcn_class(x, 0x100)) {
+        if (x != x) return x;
+        if (x < 0.0) return __builtin_nan("");
+        if (x == 0.0) return -__builtin_huge_val();
+        if (x == __builtin_huge_val()) return x;
+        x = x * 0x1p54;  // positive subnormal
         k = -54;
     }
     const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
@@ -182,15 +210,15 @@ __device__ inline double log(double x)
     const double s = div_in_range(f, 2.0 + f);  // |f| < 0.42, 2 + f in [1.7, 2.5)
     const double z = s * s;
     double R = 1.0 / 21.0;
-    R = __builtin_fma(R, z, 1.0 / 19.0);
-    R = __builtin_fma(R, z, 1.0 / 17.0);
-    R = __builtin_fma(R, z, 1.0 / 15.0);
-    R = __builtin_fma(R, z, 1.0 / 13.0);
-    R = __builtin_fma(R, z, 1.0 / 11.0);
-    R = __builtin_fma(R, z, 1.0 / 9.0);
-    R = __builtin_fma(R, z, 1.0 / 7.0);
-    R = __builtin_fma(R, z, 1.0 / 5.0);
-    R = __builtin_fma(R, z, 1.0 / 3.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 19.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 17.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 15.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 13.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 11.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 9.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 7.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 5.0);
+    R = coef_fma<kSc>(R, z, 1.0 / 3.0);
     const double s2 = 2.0 * s;
     const double log_m = __builtin_fma(s2, z * R, s2);
     const double kd = (double)k;
@@ -199,6 +227,7 @@ __device__ inline double log(double x)
 
 // cos(2 pi u): quadrant q = rint(4u); t = u - q/4 (exact) in [-1/8, 1/8];
 // theta = 2 pi t; sin and cos of theta from their Taylor series in theta^2.
+template <bool kSc = true>
 __device__ inline double cos2pi(double u)
 {
     const double q = __builtin_rint(4.0 * u);
@@ -206,23 +235,23 @@ __device__ inline double cos2pi(double u)
     const double th = t * kTau;
     const double z = th * th;
     double S = 1.0 / 355687428096000.0;
-    S = __builtin_fma(S, z, -1.0 / 1307674368000.0);
-    S = __builtin_fma(S, z, 1.0 / 6227020800.0);
-    S = __builtin_fma(S, z, -1.0 / 39916800.0);
-    S = __builtin_fma(S, z, 1.0 / 362880.0);
-    S = __builtin_fma(S, z, -1.0 / 5040.0);
-    S = __builtin_fma(S, z, 1.0 / 120.0);
-    S = __builtin_fma(S, z, -1.0 / 6.0);
+    S = coef_fma<kSc>(S, z, -1.0 / 1307674368000.0);
+    S = coef_fma<kSc>(S, z, 1.0 / 6227020800.0);
+    S = coef_fma<kSc>(S, z, -1.0 / 39916800.0);
+    S = coef_fma<kSc>(S, z, 1.0 / 362880.0);
+    S = coef_fma<kSc>(S, z, -1.0 / 5040.0);
+    S = coef_fma<kSc>(S, z, 1.0 / 120.0);
+    S = coef_fma<kSc>(S, z, -1.0 / 6.0);
     S = __builtin_fma(S, z, 1.0);
     const double sn = th * S;
     double C = -1.0 / 6402373705728000.0;
-    C = __builtin_fma(C, z, 1.0 / 20922789888000.0);
-    C = __builtin_fma(C, z, -1.0 / 87178291200.0);
-    C = __builtin_fma(C, z, 1.0 / 479001600.0);
-    C = __builtin_fma(C, z, -1.0 / 3628800.0);
-    C = __builtin_fma(C, z, 1.0 / 40320.0);
-    C = __builtin_fma(C, z, -1.0 / 720.0);
-    C = __builtin_fma(C, z, 1.0 / 24.0);
+    C = coef_fma<kSc>(C, z, 1.0 / 20922789888000.0);
+    C = coef_fma<kSc>(C, z, -1.0 / 87178291200.0);
+    C = coef_fma<kSc>(C, z, 1.0 / 479001600.0);
+    C = coef_fma<kSc>(C, z, -1.0 / 3628800.0);
+    C = coef_fma<kSc>(C, z, 1.0 / 40320.0);
+    C = coef_fma<kSc>(C, z, -1.0 / 720.0);
+    C = coef_fma<kSc>(C, z, 1.0 / 24.0);
     C = __builtin_fma(C, z, -0.5);
     C = __builtin_fma(C, z, 1.0);
     const int quadrant = ((int)q) & 3;
@@ -244,29 +273,34 @@ constexpr int kMaxInversionSteps = 10000;
 // ---------------------------------------------------------------------------
 // Samplers.
 // ---------------------------------------------------------------------------
-__device__ inline double draw_exponential(Stream& s, double rate) { return -fn::log(s.uniform()) / rate; }
-__device__ inline double draw_gamma1(Stream& s, double scale) { return -scale * fn::log(s.uniform()); }
+template <bool kSc = true>
+__device__ inline double draw_exponential(Stream& s, double rate) { return -fn::log<kSc>(s.uniform()) / rate; }
+template <bool kSc = true>
+__device__ inline double draw_gamma1(Stream& s, double scale) { return -scale * fn::log<kSc>(s.uniform()); }
 __device__ inline double draw_uniform(Stream& s, double a, double b) { return a + (b - a) * s.uniform(); }
 __device__ inline bool draw_bernoulli(Stream& s, double p) { return s.uniform() < p; }
 
 // Box-Muller, cosine branch: sqrt(-2 log u1) cos(2 pi u2).
+template <bool kSc = true>
 __device__ inline double normal_from(double u1, double u2)
 {
-    const double radius = fn::sqrt(-2.0 * fn::log(u1));
-    return radius * fn::cos2pi(u2);
+    const double radius = fn::sqrt(-2.0 * fn::log<kSc>(u1));
+    return radius * fn::cos2pi<kSc>(u2);
 }
 
+template <bool kSc = true>
 __device__ inline double draw_normal(Stream& s)
 {
     const double u1 = s.uniform();
     const double u2 = s.uniform();
-    return normal_from(u1, u2);
+    return normal_from<kSc>(u1, u2);
 }
 
+template <bool kSc = true>
 __device__ inline double draw_lognormal(Stream& s, double mu_ln, double sigma)
 {
-    const double z = draw_normal(s);
-    return fn::exp(mu_ln + sigma * z);
+    const double z = draw_normal<kSc>(s);
+    return fn::exp<kSc>(mu_ln + sigma * z);
 }
 
 // Poisson(m): inversion of the CDF, with m split into ceil(m/32) equal chunks
@@ -315,7 +349,7 @@ __device__ inline int draw_poisson(Stream& s, double m)
 // ---------------------------------------------------------------------------
 constexpr int kMaxTries = 256;
 
-__device__ inline double log_factorial(long long k)
+__device__ __forceinline__ double log_factorial(long long k)
 {
     if (k < 2) return 0.0;
     if (k < 16) {
@@ -440,7 +474,7 @@ __device__ inline double draw_lomax(Stream& s, double a, double th)
 }
 
 // log of the Binomial(z, p) probability of y, with 0 log 0 = 0.
-__device__ inline double log_binomial_pmf(long long y, long long z, double p)
+__device__ __forceinline__ double log_binomial_pmf(long long y, long long z, double p)
 {
     if (y < 0 || y > z) return -__builtin_huge_val();
     double lw = log_factorial(z) - (log_factorial(y) + log_factorial(z - y));

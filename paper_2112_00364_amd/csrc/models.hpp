@@ -164,7 +164,6 @@ struct CrbdSim {
         while (true) {
             if (entering) {
                 if (stack.depth + 1 > max_depth) return kDetected;
-                if (stack.full()) return kOverflow;
                 const double life = draw_exponential(s, mu);
                 if (life > enter_at) {
                     if (draw_bernoulli(s, rho)) return kDetected;
@@ -172,7 +171,13 @@ struct CrbdSim {
                 const double len = life < enter_at ? life : enter_at;
                 const int n = draw_poisson(s, lambda * len);
                 if (n < 0) return kDetected;
-                stack.push(CrbdFrame{n, enter_at, len});
+                // a lineage without daughters needs no frame: it is done at once
+                if (n > 0) {
+                    if (stack.full()) return kOverflow;
+                    stack.push(CrbdFrame{n, enter_at, len});
+                } else if (stack.depth == 0) {
+                    return kUndetected;
+                }
                 entering = false;
             }
             CrbdFrame& top = stack.top();
@@ -294,7 +299,6 @@ struct CrbdDsSim {
         while (true) {
             if (entering) {
                 if (stack.depth + 1 > max_depth) return kDetected;
-                if (stack.full()) return kOverflow;
                 const double life = draw_lomax(s, a_mu, th_mu);
                 a_mu = a_mu + 1.0;
                 th_mu = th_mu / (1.0 + th_mu * life);
@@ -306,7 +310,12 @@ struct CrbdDsSim {
                 if (n < 0) return kDetected;
                 a_l = a_l + (double)n;
                 th_l = th_l / (1.0 + th_l * len);
-                stack.push(CrbdFrame{(int)n, enter_at, len});
+                if (n > 0) {
+                    if (stack.full()) return kOverflow;
+                    stack.push(CrbdFrame{(int)n, enter_at, len});
+                } else if (stack.depth == 0) {
+                    return kUndetected;
+                }
                 entering = false;
             }
             CrbdFrame& top = stack.top();
@@ -450,7 +459,7 @@ struct ClaDSSide {
             if (depth > max_depth) return kDetected;
             if (events >= max_events) return kDetected;
             events += 1;
-            const double w = draw_exponential(s, rate * (1.0 + eps));
+            const double w = draw_exponential<false>(s, rate * (1.0 + eps));
             if (start - w <= 0.0) {
                 if (draw_bernoulli(s, rho)) return kDetected;
                 lineage_done = true;
@@ -458,8 +467,8 @@ struct ClaDSSide {
                 const double t = start - w;
                 if (s.uniform() < 1.0 / (1.0 + eps)) {
                     if (stack.full()) return kOverflow;
-                    const double d1 = rate * draw_lognormal(s, log_alpha, sigma);
-                    const double d2 = rate * draw_lognormal(s, log_alpha, sigma);
+                    const double d1 = rate * draw_lognormal<false>(s, log_alpha, sigma);
+                    const double d2 = rate * draw_lognormal<false>(s, log_alpha, sigma);
                     stack.push(ClaDSPending{t, d2, depth + 1});
                     start = t;
                     rate = d1;
@@ -499,24 +508,24 @@ struct Clads {
     {
         ckpt = true;
         if (b == 0) {
-            const double l0 = m.p[9] > 0.0 ? m.p[9] : draw_gamma1(s, m.p[1]);
+            const double l0 = m.p[9] > 0.0 ? m.p[9] : draw_gamma1<false>(s, m.p[1]);
             const double eps = m.p[10] >= 0.0 ? m.p[10] : draw_uniform(s, m.p[2], m.p[3]);
             const double alpha = m.p[11] > 0.0 ? m.p[11] : draw_uniform(s, m.p[4], m.p[5]);
-            const double sigma = m.p[12] >= 0.0 ? m.p[12] : draw_gamma1(s, m.p[6]);
+            const double sigma = m.p[12] >= 0.0 ? m.p[12] : draw_gamma1<false>(s, m.p[6]);
             st.eps = (double)(Real)eps;
             st.alpha = (double)(Real)alpha;
             st.sigma = (double)(Real)sigma;
             lw = lw + m.corr;
-            const double log_alpha = fn::log(st.alpha);
-            const double left = l0 * draw_lognormal(s, log_alpha, st.sigma);
-            const double right = l0 * draw_lognormal(s, log_alpha, st.sigma);
+            const double log_alpha = fn::log<false>(st.alpha);
+            const double left = l0 * draw_lognormal<false>(s, log_alpha, st.sigma);
+            const double right = l0 * draw_lognormal<false>(s, log_alpha, st.sigma);
             io.out[io.dst] = (Real)right;  // level 0
             st.lambda = (double)(Real)left;
             return m.n_nodes > 1 ? 1 : kStop;
         }
         const int node = (int)round;
         const int sp = m.sp_before[node];
-        const double log_alpha = fn::log(st.alpha);
+        const double log_alpha = fn::log<false>(st.alpha);
         ClaDSSide side{st.eps, log_alpha, st.sigma, m.p[0], 0, (int)m.p[7], (int)m.p[8]};
         double lambda = st.lambda;
         double t = m.age[m.parent[node]];
@@ -529,15 +538,15 @@ struct Clads {
                 break;
             }
             side.events += 1;
-            const double w = draw_exponential(s, lambda);
+            const double w = draw_exponential<false>(s, lambda);
             if (t - w <= tc) {
                 w_acc = w_acc + (-(st.eps * lambda) * (t - tc));
                 break;
             }
             w_acc = w_acc + (-(st.eps * lambda) * w);
             t = t - w;
-            const double cont = lambda * draw_lognormal(s, log_alpha, st.sigma);
-            const double sider = lambda * draw_lognormal(s, log_alpha, st.sigma);
+            const double cont = lambda * draw_lognormal<false>(s, log_alpha, st.sigma);
+            const double sider = lambda * draw_lognormal<false>(s, log_alpha, st.sigma);
             const int h = side.template undetected<Stack>(s, t, sider, stack);
             if (h == kOverflow) {
                 overflow = true;
@@ -562,9 +571,9 @@ struct Clads {
                 st.lambda = (double)io.in[(uint64_t)(sp - 1) * io.stride + io.src];
             }
         } else if (internal) {
-            w_acc = w_acc + fn::log(lambda);
-            const double left = lambda * draw_lognormal(s, log_alpha, st.sigma);
-            const double right = lambda * draw_lognormal(s, log_alpha, st.sigma);
+            w_acc = w_acc + fn::log<false>(lambda);
+            const double left = lambda * draw_lognormal<false>(s, log_alpha, st.sigma);
+            const double right = lambda * draw_lognormal<false>(s, log_alpha, st.sigma);
             io.out[(uint64_t)sp * io.stride + io.dst] = (Real)right;
             st.lambda = (double)(Real)left;
         } else {
