@@ -218,7 +218,7 @@ def serving_contexts(smc, ctx):
 
 
 def serving(ctx, smc, n_requests: int, budget_bytes: int, multipliers, alone_path=None, save_alone=None,
-            mode: str = "single"):
+            mode: str = "by-kind"):
     """Serving stream: every request served alone once, back to back (plain
     runs, FIFO), which gives its service time, its log Z and the
     one-at-a-time service rate; then for each multiplier m the same requests
@@ -766,7 +766,7 @@ def main():
     ap.add_argument("--no-tail-call", action="store_true",
                     help="compiled-program point: skip the tail-call form (profiles of the stack-growing form)")
     ap.add_argument("--serving-budget-gb", type=float, default=32.0)
-    ap.add_argument("--serving-mode", choices=["single", "by-kind"], default="single",
+    ap.add_argument("--serving-mode", choices=["single", "by-kind"], default="by-kind",
                     help="serving leg: one batch for all requests, or one batch per model kind on its own stream")
     ap.add_argument("--serving-alone-out", default=None,
                     help="serving leg: write the back-to-back one-at-a-time pass to this JSON file")
