@@ -403,7 +403,9 @@ smc_status smc_batch_destroy(smc_batch* b); /* NULL-safe */
  * probability of in[3i]; 11 the Negative Binomial predictive of a
  * Poisson(rate) count and 12 the Lomax predictive of an Exponential(rate)
  * lifetime, rate ~ Gamma(shape in[3i], scale in[3i+1]), first draw of the
- * stream of seed in[3i+2]. */
+ * stream of seed in[3i+2]; 13 exp, 14 log and 15 cos(2 pi u) in the form with
+ * compiler-placed polynomial coefficients (the ClaDS propagation's), which
+ * must give the same bits as ops 0-2. */
 smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n);
 /* Philox4x32-10 on n counters: ctr (device, 4 x uint32 each), key (2 x uint32
  * each), out (device, 4 x uint32 each). */

@@ -1376,7 +1376,7 @@ smc_status smc_batch_destroy(smc_batch* b)
 smc_status smc_selftest_math(smc_ctx* ctx, int32_t op, const double* in, double* out, uint64_t n)
 {
     if (!ctx || !in || !out) return fail(SMC_ERR_INVALID, "NULL argument");
-    if (op < 0 || op > 12) return fail(SMC_ERR_INVALID, "unknown op");
+    if (op < 0 || op > 15) return fail(SMC_ERR_INVALID, "unknown op");
     if (n == 0) return SMC_OK;
     HIP_TRY(launch_selftest_math(op, in, out, n, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -748,14 +748,17 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
 // The CRBD propagation is asked for 6 wavefronts per SIMD (80 VGPRs; a few
 // loop-invariant doubles move to scratch memory and are reloaded from cache):
 // 2 % faster per round than the 5 wavefronts its 89 VGPRs give by themselves.
+template <int Kind>
+constexpr int kMinWavesPerSimd = Kind == 2 ? 6 : 1;
+
 template <int Kind, class Real, int kThreads>
-__global__ __launch_bounds__(kThreads, (Kind == 2 ? 6 : 1)) void k_propagate_one(const RunDev R)
+__global__ __launch_bounds__(kThreads, kMinWavesPerSimd<Kind>) void k_propagate_one(const RunDev R)
 {
     propagate_body<Kind, Real, kThreads>(R, blockIdx.x);
 }
 
 template <int Kind, class Real, int kThreads>
-__global__ __launch_bounds__(kThreads) void k_propagate(const RunDev* __restrict__ runs,
+__global__ __launch_bounds__(kThreads, kMinWavesPerSimd<Kind>) void k_propagate(const RunDev* __restrict__ runs,
                                                         const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
@@ -1414,6 +1417,9 @@ __global__ void k_selftest_math(int op, const double* __restrict__ in, double* _
         r = draw_lomax(s, in[3 * i], in[3 * i + 1]);
         break;
     }
+    case 13: r = fn::exp<false>(in[i]); break;
+    case 14: r = fn::log<false>(in[i]); break;
+    case 15: r = fn::cos2pi<false>(in[i]); break;
     case 9: r = log_factorial((long long)in[i]); break;
     case 10: r = log_binomial_pmf((long long)in[3 * i], (long long)in[3 * i + 1], in[3 * i + 2]); break;
     default: r = 0.0;

@@ -64,9 +64,13 @@ def _edge_inputs():
             math.inf, -math.inf, 1.0 + 2 ** -52, 1.0 - 2 ** -53]
 
 
-@pytest.mark.parametrize("op", ["exp", "log", "cos2pi", "sqrt", "uniform"])
+@pytest.mark.parametrize("op", ["exp", "log", "cos2pi", "sqrt", "uniform", "exp/vreg", "log/vreg", "cos2pi/vreg"])
 def test_elementary_functions_bit_identical(ctx, oracle, op):
-    rng = np.random.default_rng(hash(op) % 2**32)
+    # "/vreg": the same function with compiler-placed coefficients (ClaDS)
+    code = {"exp": 0, "log": 1, "cos2pi": 2, "sqrt": 3, "uniform": 4, "exp/vreg": 13, "log/vreg": 14,
+            "cos2pi/vreg": 15}[op]
+    op = op.split("/")[0]
+    rng = np.random.default_rng(sum(map(ord, op)))
     n = 1 << 16
     if op == "exp":
         x = np.concatenate([rng.uniform(-708, 709, n), rng.uniform(-40, 0, n), _edge_inputs()])
@@ -84,8 +88,7 @@ def test_elementary_functions_bit_identical(ctx, oracle, op):
     else:
         x = np.concatenate([rng.integers(0, 2**32, size=n).astype(np.float64), [0.0, 2.0**32 - 1]])
         ref = [oracle.uniform_from_word(int(v)) for v in x]
-    code = {"exp": 0, "log": 1, "cos2pi": 2, "sqrt": 3, "uniform": 4}[op]
-    say("selftest", op, len(x))
+    say("selftest", op, code, len(x))
     got = ctx.selftest_math(code, x)
     ref = np.array(ref)
     same = (bits(got) == bits(ref)) | (np.isnan(got) & np.isnan(ref))
