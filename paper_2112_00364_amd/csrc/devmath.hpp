@@ -117,6 +117,14 @@ __device__ inline double fma_sc(double a, double b, double c)
     return r;
 }
 
+// a * b + c rounded once, with the constant b read from scalar registers.
+__device__ inline double fma_vsv(double a, double b, double c)
+{
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 // One polynomial step. kScalarCoef: the coefficient is read from scalar
 // registers (fma_sc), which keeps it out of the vector register file and the
 // vector instruction stream - the better placement where many wavefronts share
@@ -353,21 +361,26 @@ __device__ __forceinline__ double log_factorial(long long k)
 {
     if (k < 2) return 0.0;
     if (k < 16) {
+        // log i for i < 16 are compile-time constants (the compiler folds the
+        // compiler-placed form of log on constant arguments); they are added
+        // in order, each times 1 (i <= k) or 0 (adds nothing), with the
+        // constant read from scalar registers.
         double s = 0.0;
-        for (long long i = 2; i <= k; ++i) s = s + fn::log((double)i);
+#pragma unroll
+        for (int i = 2; i < 16; ++i) s = fn::fma_vsv(i <= k ? 1.0 : 0.0, fn::log<false>((double)i), s);
         return s;
     }
     const double x = (double)(k + 1);
     const double x2 = x * x;
     const double series = (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0 - 1.0 / (1680.0 * x2)) / x2) / x2) / x;
-    return ((x - 0.5) * fn::log(x) - x) + (0.5 * fn::log(fn::kTau) + series);
+    return ((x - 0.5) * fn::log(x) - x) + (0.5 * fn::log<false>(fn::kTau) + series);  // a folded constant
 }
 
 // log k! - [(k + 1/2) log(k + 1) - (k + 1) + log(2 pi) / 2]
 __device__ inline double stirling_tail(long long k)
 {
     const double x = (double)(k + 1);
-    return log_factorial(k) - ((((double)k + 0.5) * fn::log(x) - x) + 0.5 * fn::log(fn::kTau));
+    return log_factorial(k) - ((((double)k + 0.5) * fn::log(x) - x) + 0.5 * fn::log<false>(fn::kTau));
 }
 
 __device__ inline double draw_gamma(Stream& s, double a)
