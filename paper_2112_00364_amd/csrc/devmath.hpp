@@ -372,7 +372,10 @@ __device__ __forceinline__ double log_factorial(long long k)
     }
     const double x = (double)(k + 1);
     const double x2 = x * x;
-    const double series = (1.0 / 12.0 - (1.0 / 360.0 - (1.0 / 1260.0 - 1.0 / (1680.0 * x2)) / x2) / x2) / x;
+    // x >= 17: every quotient is inside div_in_range's range
+    const double series = fn::div_in_range(
+        1.0 / 12.0 - fn::div_in_range(1.0 / 360.0 - fn::div_in_range(1.0 / 1260.0 - fn::div_in_range(1.0, 1680.0 * x2), x2), x2),
+        x);
     return ((x - 0.5) * fn::log(x) - x) + (0.5 * fn::log<false>(fn::kTau) + series);  // a folded constant
 }
 
@@ -415,7 +418,7 @@ __device__ inline long long binomial_small(Stream& s, long long n, double p)
     while (u > pk && k < n) {
         u = u - pk;
         k += 1;
-        pk = pk * ((double)(n - k + 1) / (double)k * ratio);
+        pk = pk * (fn::div_in_range((double)(n - k + 1), (double)k) * ratio);
     }
     return k;
 }
@@ -427,23 +430,23 @@ __device__ inline long long binomial_btrs(Stream& s, long long n, double p)
     const double b = 1.15 + 2.53 * spq;
     const double a = -0.0873 + 0.0248 * b + 0.01 * p;
     const double c = (double)n * p + 0.5;
-    const double v_r = 0.92 - 4.2 / b;
-    const double r = p / q;
-    const double alpha = (2.83 + 5.1 / b) * spq;
+    const double v_r = 0.92 - fn::div_in_range(4.2, b);
+    const double r = fn::div_in_range(p, q);
+    const double alpha = (2.83 + fn::div_in_range(5.1, b)) * spq;
     const long long m = (long long)__builtin_floor((double)(n + 1) * p);
-    const double h = ((double)m + 0.5) * fn::log(((double)m + 1.0) / (r * (double)(n - m + 1))) +
+    const double h = ((double)m + 0.5) * fn::log(fn::div_in_range((double)m + 1.0, r * (double)(n - m + 1))) +
                      (stirling_tail(m) + stirling_tail(n - m));
     for (int it = 0; it < kMaxTries; ++it) {
         const double u = s.uniform() - 0.5;
         const double v = s.uniform();
         const double us = 0.5 - __builtin_fabs(u);
-        const double kf = __builtin_floor((2.0 * a / us + b) * u + c);
+        const double kf = __builtin_floor((fn::div_in_range(2.0 * a, us) + b) * u + c);
         if (us >= 0.07 && v <= v_r) return (long long)kf;
         if (kf < 0.0 || kf > (double)n) continue;
         const long long k = (long long)kf;
-        const double lv = fn::log(v * alpha / (a / (us * us) + b));
-        const double bound = h + ((double)(n + 1) * fn::log((double)(n - m + 1) / (double)(n - k + 1)) +
-                                  ((double)k + 0.5) * fn::log(r * (double)(n - k + 1) / ((double)k + 1.0))) -
+        const double lv = fn::log(fn::div_in_range(v * alpha, fn::div_in_range(a, us * us) + b));
+        const double bound = h + ((double)(n + 1) * fn::log(fn::div_in_range((double)(n - m + 1), (double)(n - k + 1))) +
+                                  ((double)k + 0.5) * fn::log(fn::div_in_range(r * (double)(n - k + 1), (double)k + 1.0))) -
                              (stirling_tail(k) + stirling_tail(n - k));
         if (lv <= bound) return k;
     }
