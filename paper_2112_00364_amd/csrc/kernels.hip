@@ -745,20 +745,14 @@ __device__ __forceinline__ void propagate_body(const RunDev& R, uint32_t tile)
 
 // Entry points: one run (its record is a kernel argument, tile = work-group)
 // or a batch (work-group -> (run, tile) table).
-// The CRBD propagation is asked for 6 wavefronts per SIMD (80 VGPRs; a few
-// loop-invariant doubles move to scratch memory and are reloaded from cache):
-// 2 % faster per round than the 5 wavefronts its 89 VGPRs give by themselves.
-template <int Kind>
-constexpr int kMinWavesPerSimd = Kind == 2 ? 6 : 1;
-
 template <int Kind, class Real, int kThreads>
-__global__ __launch_bounds__(kThreads, kMinWavesPerSimd<Kind>) void k_propagate_one(const RunDev R)
+__global__ __launch_bounds__(kThreads) void k_propagate_one(const RunDev R)
 {
     propagate_body<Kind, Real, kThreads>(R, blockIdx.x);
 }
 
 template <int Kind, class Real, int kThreads>
-__global__ __launch_bounds__(kThreads, kMinWavesPerSimd<Kind>) void k_propagate(const RunDev* __restrict__ runs,
+__global__ __launch_bounds__(kThreads) void k_propagate(const RunDev* __restrict__ runs,
                                                         const TileRef* __restrict__ tiles)
 {
     const TileRef tr = tiles[blockIdx.x];
