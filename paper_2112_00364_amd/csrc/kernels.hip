@@ -891,7 +891,7 @@ __global__ __launch_bounds__(kRedThreads) void k_bucket_scatter(const RunDev R)
 // ---------------------------------------------------------------------------
 // Reduction: M, then per-tile sums of exp(lw - M) and grid units.
 // ---------------------------------------------------------------------------
-constexpr int kFoldThreads = 1024;
+constexpr int kFoldThreads = 512;
 
 // Publishes the round's fold of the propagation partials (one writer per run).
 __device__ inline void publish_fold(const RunDev& R, RunCtl* ctl, const Partial& f)
@@ -1013,7 +1013,7 @@ __device__ inline void finish_round(const RunDev& R, RunCtl* ctl, bool bad, bool
 // tile sums and writes the tile offsets.
 // Tiles folded per thread: kFoldPer x kFoldThreads tiles of kTileRed particles
 // cover the largest run (2^24 particles).
-constexpr uint32_t kFoldPer = 16;
+constexpr uint32_t kFoldPer = 32;
 static_assert((unsigned long long)kFoldPer * kFoldThreads * kTileRed >= (1ull << 24), "fold covers 2^24 particles");
 
 __device__ __forceinline__ void fold_sums_body(const RunDev& R)
@@ -1022,19 +1022,18 @@ __device__ __forceinline__ void fold_sums_body(const RunDev& R)
     RunCtl* ctl = R.ctl;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t T = R.red_tiles;
-    const uint32_t per = (T + kFoldThreads - 1) / kFoldThreads;
-    const uint32_t t0 = threadIdx.x * per;
-    const uint32_t t1 = t0 + per < T ? t0 + per : T;
     const bool ess = R.ess_t != 0;
-    // every tile sum this thread folds is requested at once, before the
-    // control block is consumed (zeros past the thread's tiles leave the
-    // sums' bits unchanged: they are non-negative)
-    double q_local = 0.0, e_local = 0.0;
+    // Tile t sits in row t / kFoldThreads, column t % kFoldThreads: thread c
+    // holds column c, so every load of a row is one coalesced access. All tile
+    // sums are requested at once, before the control block is consumed (zeros
+    // past the last tile leave every sum unchanged: they are non-negative).
+    double qv[kFoldPer];
+    double e_local = 0.0;
 #pragma unroll
     for (uint32_t i = 0; i < kFoldPer; ++i) {
-        const bool mine = i < per && t0 + i < T;
-        q_local += mine ? R.part_q[t0 + i] : 0.0;
-        e_local += mine ? R.part_e[t0 + i] : 0.0;
+        const uint32_t t = i * kFoldThreads + threadIdx.x;
+        qv[i] = t < T ? R.part_q[t] : 0.0;
+        e_local += t < T ? R.part_e[t] : 0.0;
     }
     if (ctl->status != 0) return;
     const bool bad = ctl->bad != 0;
@@ -1042,47 +1041,64 @@ __device__ __forceinline__ void fold_sums_body(const RunDev& R)
     const bool usable = !bad && ctl->maxkey != 0 && M != -__builtin_huge_val();
     U128 q2_local{0ull, 0ull};
     if (!usable) {
-        q_local = 0.0;
+#pragma unroll
+        for (uint32_t i = 0; i < kFoldPer; ++i) qv[i] = 0.0;
         e_local = 0.0;
     }
-    if (usable) {
-        if (ess)
-            for (uint32_t t = t0; t < t1; ++t) q2_local = add128(q2_local, U128{R.part_q2[2 * t + 1], R.part_q2[2 * t]});
+    if (usable && ess)
+        for (uint32_t t = threadIdx.x; t < T; t += kFoldThreads)
+            q2_local = add128(q2_local, U128{R.part_q2[2 * t + 1], R.part_q2[2 * t]});
+    // Exclusive prefix of every tile in row-major order: the rows before it,
+    // the wavefronts before it in its row, the lanes before it in its
+    // wavefront. The q sums are integer-valued and below 2^53, so every
+    // partial sum is exact and the order of the additions does not matter.
+    constexpr int kWaves = kFoldThreads / 64;
+    __shared__ double s_row_wave[kFoldPer][kWaves];  // wavefront totals per row
+    __shared__ double s_ew[kWaves];
+    __shared__ U128 s_q2w[kWaves];
+#pragma unroll
+    for (uint32_t i = 0; i < kFoldPer; ++i) {
+        const double incl = wave_incl_scan<OpAddF64>(qv[i]);
+        if (lane == 63) s_row_wave[i][wave] = incl;
+        qv[i] = incl - qv[i];  // exclusive within the wavefront (exact)
     }
-    const double q_incl = wave_incl_scan<OpAddF64>(q_local);  // exact: integer-valued
     const double e_wave = wave_sum(e_local);
     const U128 q2_wave = ess ? wave_sum(q2_local) : U128{0ull, 0ull};
-    __shared__ double s_qw[kFoldThreads / 64], s_ew[kFoldThreads / 64];
-    __shared__ U128 s_q2w[kFoldThreads / 64];
-    if (lane == 63) s_qw[wave] = q_incl;
     if (lane == 0) {
         s_ew[wave] = e_wave;
         s_q2w[wave] = q2_wave;
     }
     __syncthreads();
-    double q_before = 0.0, q_all = 0.0, e_all = 0.0;
+    // one lane per row: the wavefront totals become offsets within the row
+    __shared__ double s_row_total[kFoldPer];
+    if (threadIdx.x < kFoldPer) {
+        const uint32_t i = threadIdx.x;
+        double run = 0.0;
+        for (int w = 0; w < kWaves; ++w) {
+            const double x = s_row_wave[i][w];
+            s_row_wave[i][w] = run;
+            run += x;
+        }
+        s_row_total[i] = run;
+    }
+    __syncthreads();
+    double q_all = 0.0, e_all = 0.0;
     U128 q2_all{0ull, 0ull};
-    for (int w = 0; w < kFoldThreads / 64; ++w) {
-        if (w < wave) q_before += s_qw[w];
-        q_all += s_qw[w];
+    for (uint32_t i = 0; i < kFoldPer; ++i) q_all += s_row_total[i];
+    for (int w = 0; w < kWaves; ++w) {
         e_all += s_ew[w];
         q2_all = add128(q2_all, s_q2w[w]);
     }
     const bool active = ctl->active != 0;
     const bool resample = active && ess_says_resample(R.ess_t, R.n, q_all, q2_all);
     if (usable && resample) {
-        double run = q_before + (q_incl - q_local);
-        // all of this thread's tile sums in registers first: a load placed
-        // after a store to prefix could not be moved above it
-        double qv[kFoldPer];
+        double row_base = 0.0;
 #pragma unroll
-        for (uint32_t i = 0; i < kFoldPer; ++i) qv[i] = (i < per && t0 + i < T) ? R.part_q[t0 + i] : 0.0;
-#pragma unroll
-        for (uint32_t i = 0; i < kFoldPer; ++i)
-            if (i < per && t0 + i < T) {
-                R.prefix[t0 + i] = run;
-                run += qv[i];
-            }
+        for (uint32_t i = 0; i < kFoldPer; ++i) {
+            const uint32_t t = i * kFoldThreads + threadIdx.x;
+            if (t < T) R.prefix[t] = row_base + s_row_wave[i][wave] + qv[i];
+            row_base += s_row_total[i];
+        }
     }
     if (threadIdx.x == 0) {
         ctl->m_cur = M;
