@@ -138,7 +138,10 @@ def _weights(kind, n, rng):
     raise ValueError(kind)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 1000, 1023, 1024, 1025, 4096 + 17, 65536, 1 << 20])
+# above 2^20 the tile sums go through the fold kernel: 1025 tiles (one tile past the
+# fused path) and 3085 tiles (six full rows of 512 and a ragged seventh)
+@pytest.mark.parametrize("n", [1, 2, 3, 1000, 1023, 1024, 1025, 4096 + 17, 65536, 1 << 20, (1 << 20) + 1,
+                               3 * (1 << 20) + 12345])
 @pytest.mark.parametrize("kind", ["normal", "wide", "equal", "single", "tiny"])
 def test_resample_weights_matches_oracle(ctx, oracle, n, kind):
     rng = np.random.default_rng(n * 31 + len(kind))
