@@ -32,6 +32,21 @@ def test_algorithmic_bytes_per_round():
     assert bench.STEPS["propagate"] == ("propagate", "hidden")
 
 
+def test_clads_run_bytes_counts_the_live_stack():
+    # Three-tip tree in preorder: root 0 -> (1, 4); node 1 -> (2, 3). The walk
+    # visits nodes 1..4 with 1, 2, 1, 0 pending rates below them (one left at
+    # the root; internal node 1 pushes one; each tip pops one).
+    tree = {"left": [1, 2, -1, -1, -1]}
+    n = 10
+    per = 29                              # round 0: block 1 + state 16 + level 0 4 + lw 8
+    per += 46 + 8 * 1 + 4                 # node 1, internal, sp = 1
+    per += 46 + 8 * 2                     # node 2, tip, sp = 2
+    per += 46 + 8 * 1                     # node 3, tip, sp = 1
+    per += 46 + 8 * 0                     # node 4, tip, sp = 0
+    per += 20 * 4 + 8                     # four resampling rounds, the last one only reads lw
+    assert bench.clads_run_bytes(tree, n) == n * per
+
+
 def test_traffic_record_only_for_current_kernels(tmp_path, monkeypatch):
     """Traffic per round of a step: every dispatch of the step's kernels in the
     profiled runs, over runs x rounds; only while the record's kernel sources
