@@ -121,8 +121,10 @@ def clads_run_bytes(tree, n: int) -> float:
 def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16, tune=True, cache_path=None):
     """512 independent ClaDS runs (trees of 32-128 tips, seeds 4000 + r), 4096
     particles each, advanced together by the batch API. Before the timed
-    region the batch autotuner picks each run shape's propagation work-group
-    size (cached in a JSON file, tuned on a probe batch the first time)."""
+    region the batch autotuner picks each run shape's launch option -- the
+    propagation work-group size of the segmented launches, or one work-group
+    owning each run -- cached in a JSON file, tuned on a probe batch the first
+    time."""
     import numpy as np
     import torch
     from paper_2112_00364_amd import autotune as A
@@ -139,13 +141,13 @@ def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16, tune=True, 
         for r, t in enumerate(tips):
             key = A.shape_key("clads", 32, n, int(t))
             if key not in lanes:
-                lanes[key] = A.batch_workgroup(cache, ctx, models[r], "clads", 32, n, int(t))
+                lanes[key] = A.batch_launch(cache, ctx, models[r], "clads", 32, n, int(t))
         tune_s = time.perf_counter() - t0
     b = smc.Batch(ctx)
     for r, m in enumerate(models):
         slot = b.add(m, n, 40000 + r)
         if tune:
-            b.set_workgroup(slot, lanes[A.shape_key("clads", 32, n, int(tips[r]))])
+            A.apply_batch_launch(b, slot, lanes[A.shape_key("clads", 32, n, int(tips[r]))])
     b.tick(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -167,13 +169,56 @@ def batched_clads(ctx, smc, I, runs=512, n=4096, rounds_per_tick=16, tune=True, 
     return {"workload": f"clads_batch_{runs}x{n}", "runs": runs, "particles_per_run": n,
             "tips": [int(tips.min()), int(tips.max())], "seconds": dt, "block_steps": total,
             "block_steps_per_s": total / dt, "finished_runs": ok, "rounds_per_tick": rounds_per_tick,
-            "workgroup_lanes": lanes, "autotune": {key: cache.get(key) for key in lanes},
+            "launch_choice": lanes, "autotune": {key: cache.get(key) for key in lanes},
             "autotune_seconds": tune_s,
             # the whole leg (every launch of every tick) against HBM: the batch is bound by its
             # longest dependent chains, not by memory
             "roofline": {"bound": "hbm", "achieved": round(alg_bytes / dt / 1e9, 3), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(alg_bytes / dt / 1e9 / HBM_PEAK_GBS, 6), "traffic": None,
                          "kernel": "all launches of the leg", "alg_bytes": alg_bytes}}
+
+
+def owned_point(ctx, smc, I, rounds_per_tick=16):
+    """Whole batches run to the end with segmented launches and with every run
+    owned by one work-group (smc_batch_set_owned): seconds each and whether the
+    log Z bits agree. Trees of 32-128 tips (seed 5), seeds 40000 + r."""
+    import numpy as np
+    import torch
+
+    def whole(models, ns, owned):
+        b = smc.Batch(ctx)
+        slots = [b.add(m, n, 40000 + i) for i, (m, n) in enumerate(zip(models, ns))]
+        for s in slots:
+            if owned:
+                b.set_owned(s)
+        b.tick(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while True:
+            b.tick(rounds_per_tick)
+            done, lz, st, steps = b.poll()
+            if done.all():
+                break
+        dt = time.perf_counter() - t0
+        b.close()
+        return dt, [float(x) for x in lz[:len(slots)]], int(steps.sum())
+
+    out = {}
+    rng = np.random.default_rng(5)
+    for name, kind, count, n in (("crbd_16x256", "crbd", 16, 256), ("crbd_256x1024", "crbd", 256, 1024),
+                                 ("crbd_64x4096", "crbd", 64, 4096), ("clads_128x1024", "clads", 128, 1024),
+                                 ("clads_512x4096", "clads", 512, 4096)):
+        tips = rng.integers(32, 129, size=count)
+        make = I.crbd_spec if kind == "crbd" else I.clads_spec
+        models = [smc.Model(ctx, make(I.yule_tree(int(t), 4000 + r), precision=32)) for r, t in enumerate(tips)]
+        seg = whole(models, [n] * count, False)
+        own = whole(models, [n] * count, True)
+        for m in models:
+            m.close()
+        out[name] = {"segmented_s": seg[0], "owned_s": own[0], "block_steps": seg[2],
+                     "same_log_z": seg[1] == own[1]}
+        print(f"owned: {name} segmented {seg[0]:.3f} s, owned {own[0]:.3f} s", file=sys.stderr, flush=True)
+    return out
 
 
 def _clads_oracle_run(job):
@@ -773,7 +818,7 @@ def main():
     ap.add_argument("--serving-alone-in", default=None,
                     help="serving leg: take the one-at-a-time pass from this JSON file instead of measuring it")
     ap.add_argument("--only", choices=["ess", "crbd_ds", "seir", "seir_program", "bucketing", "large", "kalman",
-                                       "small", "batched", "serving"],
+                                       "small", "batched", "serving", "owned"],
                     help="run this one leg alone (no headline runs) and print its record: "
                          "for kernel traces that hold one workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -813,6 +858,7 @@ def main():
                 "kalman": lambda: kalman_point(smc, ctx, I),
                 "small": lambda: small_crbd_point(smc, ctx, I, cpu=not args.no_cpu_baseline),
                 "batched": lambda: batched_clads(ctx, smc, I, tune=not args.no_autotune),
+                "owned": lambda: owned_point(ctx, smc, I),
                 "serving": lambda: serving(ctx, smc, args.serving_requests, int(args.serving_budget_gb * 2**30),
                                            rates, args.serving_alone_in, args.serving_alone_out,
                                            args.serving_mode)}

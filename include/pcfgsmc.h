@@ -359,13 +359,17 @@ smc_status smc_resample_weights(smc_ctx* ctx, const double* lw, uint64_t n, uint
 smc_status smc_resample_weights_noalloc(smc_ctx* ctx, const double* lw, uint64_t n, uint64_t seed,
                                         uint32_t round, uint32_t* anc, double* logz_inc);
 
-/* Batches: many independent runs advanced together. Every round of a tick is
- * one propagation launch per (model kind, precision, work-group size) group
- * over a (run, tile) table of all live runs, then one reduction and one scan
- * launch over a table of every run's reduction tiles; each run's tiles read
- * that run's own control block, so runs of different sizes, trees and round
- * counts share the launches and finished runs drop out at once. Results are
- * identical to the same runs executed alone. */
+/* Batches: many independent runs advanced together (the batching of many SMC
+ * runs on one GPU; the paper's engine runs one). Segmented runs: every round
+ * of a tick is one propagation launch per (model kind, precision, work-group
+ * size) group over a (run, tile) table of all live runs, then one reduction
+ * and one scan launch over a table of every run's reduction tiles; each run's
+ * tiles read that run's own control block, so runs of different sizes, trees
+ * and round counts share the launches and finished runs drop out at once.
+ * Owned runs (smc_batch_set_owned): one work-group advances the run through
+ * all the rounds of a tick by itself, one launch per (kind, precision) for
+ * all such runs, so each moves at its own pace. Results are identical to the
+ * same runs executed alone either way. */
 smc_status smc_batch_create(smc_ctx* ctx, smc_batch** out);
 /* Add a run (Algorithm 1 step 1 for it); *slot receives its index. The model
  * may be registered on another context of the same device (registration
@@ -381,6 +385,12 @@ smc_status smc_batch_add(smc_batch* b, smc_model* model, uint64_t n_particles, u
  * autotuner, results unchanged). The run's tiles move to the launch group of
  * that size at the next tick. */
 smc_status smc_batch_set_workgroup(smc_batch* b, int32_t slot, int32_t lanes);
+/* owned != 0: from the next tick one work-group of 256 lanes owns the run in
+ * `slot` through every round of each tick (its propagation, reduction and
+ * scan tiles in turn); owned == 0: back to the segmented launches. Only
+ * built-in models (not SMC_MODEL_PROGRAM) of at most 4096 particles can be
+ * owned (SMC_ERR_INVALID otherwise). A launch option, results unchanged. */
+smc_status smc_batch_set_owned(smc_batch* b, int32_t slot, int32_t owned);
 smc_status smc_batch_tick(smc_batch* b, int32_t rounds);
 /* Synchronises. done[i] = 1 for finished (or failed) slots; log_z[i] their
  * estimates; status[i] their status. Arrays are host, length = slots. */

@@ -108,21 +108,27 @@ class LaunchCache:
 
 
 def choose_batch_workgroup(ctx, model, n: int, seeds, rounds: int = 8, ticks: int = 2,
-                           lanes=(128, 256)) -> dict:
+                           lanes=(128, 256), owned: bool = False) -> dict:
     """Times a probe batch of len(seeds) runs of `model` (n particles each)
-    advanced `ticks` ticks of `rounds` rounds under each work-group size, from
-    the same initial particles every time (fresh batches, same seeds); the
-    fastest size wins. The probe's results are discarded."""
+    advanced `ticks` ticks of `rounds` rounds under each launch option -- each
+    propagation work-group size of the segmented launches and, with `owned`,
+    one work-group owning each run -- from the same initial particles every
+    time (fresh batches, same seeds); the fastest option wins. The probe's
+    results are discarded."""
     import torch
     from . import smc
+    options = [(f"lanes{l}", l, False) for l in lanes] + ([("owned", 256, True)] if owned else [])
     times = {}
-    for l in lanes:
+    for name, l, own in options:
         best = None
         for _ in range(2):
             b = smc.Batch(ctx)
             slots = [b.add(model, n, s) for s in seeds]
             for slot in slots:
-                b.set_workgroup(slot, l)
+                if own:
+                    b.set_owned(slot)
+                else:
+                    b.set_workgroup(slot, l)
             b.tick(0)  # tables
             torch.cuda.synchronize()
             start = torch.cuda.Event(enable_timing=True)
@@ -135,18 +141,40 @@ def choose_batch_workgroup(ctx, model, n: int, seeds, rounds: int = 8, ticks: in
             t = start.elapsed_time(end)
             best = t if best is None else min(best, t)
             b.close()
-        times[l] = best
+        times[name] = best
     choice = min(times, key=times.get)
-    return {"lanes": choice, "rounds": rounds, "ticks": ticks, "runs": len(seeds),
-            "ms": {f"lanes{l}": t for l, t in times.items()}}
+    lanes_of = {name: l for name, l, _ in options}
+    return {"lanes": lanes_of[choice], "owned": choice == "owned", "rounds": rounds, "ticks": ticks,
+            "runs": len(seeds), "ms": times}
+
+
+# Largest run one work-group may own (smc_batch_set_owned).
+OWNED_MAX_PARTICLES = 4096
+
+
+def batch_launch(cache: LaunchCache, ctx, model, kind: str, precision: int, n: int, tips: int,
+                 probe_runs: int = 8) -> dict:
+    """The cached launch option for this run shape, tuned on first use:
+    {"lanes": 128 or 256, "owned": bool}. Owning by a work-group is tried for
+    built-in models of at most OWNED_MAX_PARTICLES particles."""
+    key = shape_key(kind, precision, n, tips)
+    hit = cache.get(key)
+    if hit is None or "owned" not in hit:
+        can_own = kind != "program" and n <= OWNED_MAX_PARTICLES
+        hit = choose_batch_workgroup(ctx, model, n, seeds=list(range(90001, 90001 + probe_runs)), owned=can_own)
+        cache.put(key, hit)
+    return {"lanes": int(hit["lanes"]), "owned": bool(hit["owned"])}
+
+
+def apply_batch_launch(batch, slot: int, choice: dict):
+    """Applies a batch_launch choice to one run of a batch."""
+    if choice["owned"]:
+        batch.set_owned(slot)
+    else:
+        batch.set_workgroup(slot, choice["lanes"])
 
 
 def batch_workgroup(cache: LaunchCache, ctx, model, kind: str, precision: int, n: int, tips: int,
                     probe_runs: int = 8) -> int:
-    """The cached work-group size for this run shape, tuned on first use."""
-    key = shape_key(kind, precision, n, tips)
-    hit = cache.get(key)
-    if hit is None:
-        hit = choose_batch_workgroup(ctx, model, n, seeds=list(range(90001, 90001 + probe_runs)))
-        cache.put(key, hit)
-    return int(hit["lanes"])
+    """The cached work-group size of the segmented launches for this run shape."""
+    return batch_launch(cache, ctx, model, kind, precision, n, tips, probe_runs)["lanes"]

@@ -280,6 +280,7 @@ struct smc_run {
     RunDev* dev = nullptr;
     uint32_t n_prop = 0, n_red = 0;
     bool expect_step = true;   // Alg. 1: step 2 and step 3 alternate
+    bool owned = false;        // batched: one work-group advances it through a tick
     uint32_t rounds_issued = 0;
     int32_t known_status = SMC_OK;
     DeviceArena arena;
@@ -1119,6 +1120,13 @@ struct smc_batch {
         uint32_t n;
     };
     std::vector<Group> groups;
+    struct Owned {  // runs owned by one work-group each, one launch per tick
+        int kind, precision;
+        uint32_t* ids;
+        uint32_t n;
+    };
+    std::vector<Owned> owned;
+    std::vector<std::vector<uint32_t>> owned_ids_h;
     TileRef* red_tiles = nullptr;
     uint32_t n_red = 0;
     std::vector<RunDev> runs_h;
@@ -1147,6 +1155,8 @@ void clear_tables(smc_batch* b)
     b->red_tiles = nullptr;
     b->n_red = 0;
     b->groups.clear();
+    b->owned.clear();
+    b->owned_ids_h.clear();
     b->runs_h.clear();
     b->group_tiles_h.clear();
     b->red_tiles_h.clear();
@@ -1172,11 +1182,23 @@ smc_status rebuild_tables(smc_batch* b)
         int kind, precision, lanes;
     };
     std::vector<Key> keys;
+    std::vector<Key> owned_keys;
     for (smc_run* r : b->slots) {
         if (!r) continue;
         const uint32_t idx = (uint32_t)b->runs_h.size();
         b->runs_h.push_back(r->host);
         if (!r->host.fused) b->any_unfused = true;
+        if (r->owned) {
+            size_t g = 0;
+            for (; g < owned_keys.size(); ++g)
+                if (owned_keys[g].kind == r->model->kind && owned_keys[g].precision == r->model->precision) break;
+            if (g == owned_keys.size()) {
+                owned_keys.push_back(Key{r->model->kind, r->model->precision, 0});
+                b->owned_ids_h.emplace_back();
+            }
+            b->owned_ids_h[g].push_back(idx);
+            continue;
+        }
         size_t g = 0;
         const int lanes = (int)r->host.lanes;
         for (; g < keys.size(); ++g)
@@ -1198,14 +1220,25 @@ smc_status rebuild_tables(smc_batch* b)
         return s;
     };
     b->runs = (RunDev*)b->tables.get(sizeof(RunDev) * b->runs_h.size());
-    b->red_tiles = (TileRef*)b->tables.get(sizeof(TileRef) * b->red_tiles_h.size());
-    if (!b->runs || !b->red_tiles) return undo(fail(SMC_ERR_OOM, "batch table allocation failed"));
+    // every run may be owned by a work-group: then there are no tile tables
+    const bool any_tiles = !b->red_tiles_h.empty();
+    b->red_tiles = any_tiles ? (TileRef*)b->tables.get(sizeof(TileRef) * b->red_tiles_h.size()) : nullptr;
+    if (!b->runs || (any_tiles && !b->red_tiles)) return undo(fail(SMC_ERR_OOM, "batch table allocation failed"));
     hipError_t e = hipMemcpyAsync(b->runs, b->runs_h.data(), sizeof(RunDev) * b->runs_h.size(),
                                   hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && any_tiles)
         e = hipMemcpyAsync(b->red_tiles, b->red_tiles_h.data(), sizeof(TileRef) * b->red_tiles_h.size(),
                            hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return undo(fail(SMC_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e)));
+    for (size_t g = 0; g < owned_keys.size(); ++g) {
+        const size_t bytes = sizeof(uint32_t) * b->owned_ids_h[g].size();
+        uint32_t* ids = (uint32_t*)b->tables.get(bytes);
+        if (!ids) return undo(fail(SMC_ERR_OOM, "batch table allocation failed"));
+        e = hipMemcpyAsync(ids, b->owned_ids_h[g].data(), bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return undo(fail(SMC_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e)));
+        b->owned.push_back(smc_batch::Owned{owned_keys[g].kind, owned_keys[g].precision, ids,
+                                            (uint32_t)b->owned_ids_h[g].size()});
+    }
     for (size_t g = 0; g < keys.size(); ++g) {
         TileRef* t = (TileRef*)b->tables.get(sizeof(TileRef) * b->group_tiles_h[g].size());
         if (!t) return undo(fail(SMC_ERR_OOM, "batch table allocation failed"));
@@ -1278,6 +1311,19 @@ smc_status smc_batch_set_workgroup(smc_batch* b, int32_t slot, int32_t lanes)
     return SMC_OK;
 }
 
+smc_status smc_batch_set_owned(smc_batch* b, int32_t slot, int32_t owned)
+{
+    if (!b) return fail(SMC_ERR_INVALID, "NULL batch");
+    if (slot < 0 || (size_t)slot >= b->slots.size() || !b->slots[slot]) return fail(SMC_ERR_INVALID, "no such slot");
+    smc_run* r = b->slots[slot];
+    if (owned && (r->model->kind == SMC_MODEL_PROGRAM || r->n > kOwnedMaxParticles))
+        return fail(SMC_ERR_INVALID, "a work-group owns only built-in models of at most 4096 particles");
+    if (r->owned == (owned != 0)) return SMC_OK;
+    r->owned = owned != 0;
+    b->dirty = true;
+    return SMC_OK;
+}
+
 smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
 {
     if (!b || rounds < 0) return fail(SMC_ERR_INVALID, "bad argument");
@@ -1289,6 +1335,11 @@ smc_status smc_batch_tick(smc_batch* b, int32_t rounds)
     hipStream_t st = b->ctx->stream;
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         const uint32_t n_runs = (uint32_t)b->runs_h.size();
+        for (const auto& o : b->owned) {  // every round of the tick in one launch
+            const hipError_t e = launch_owned(o.kind, o.precision, b->runs, o.ids, o.n, (uint32_t)rounds, s);
+            if (e != hipSuccess) return e;
+        }
+        if (b->groups.empty() && b->n_red == 0) return hipSuccess;  // no segmented runs
         for (int32_t k = 0; k < rounds; ++k) {
             for (const auto& g : b->groups) {
                 const hipError_t e = launch_propagate(g.kind, g.precision, g.lanes, b->runs, g.tiles, g.n, s);

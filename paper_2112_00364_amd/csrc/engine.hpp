@@ -73,6 +73,9 @@ constexpr int kTileRed = kRedThreads * kRedItems;  // particles per reduction ti
 // reduction's tile sums inside the scan kernel; larger runs use the
 // one-work-group fold kernel.
 constexpr uint32_t kMaxFusedRedTiles = 1024;
+// A batched run of at most this many particles may be owned by one work-group
+// (kRedThreads lanes) for all the rounds of a tick.
+constexpr uint32_t kOwnedMaxParticles = 4 * kTileRed;
 // Block bucketing sorts slots by their resume block (255 = b_stop) into
 // kBuckets keys, over the reduction tiles.
 constexpr int kBuckets = 256;

@@ -1323,6 +1323,43 @@ __global__ __launch_bounds__(kRedThreads) void k_scan_anc(const RunDev* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Batched runs owned by one work-group each.
+// ---------------------------------------------------------------------------
+// A run of at most kOwnedMaxParticles particles is advanced by one work-group
+// through every round of a tick: its propagation tiles, then its reduction
+// tiles, then its scan tiles, one after another with the work-group's
+// barriers between them, so the run moves at its own pace and costs no launch
+// per round. The steps are the bodies the segmented launches run, in an order
+// they accept (tile 0, which writes the control block, last), so every run
+// gets the same bits either way.
+template <int Kind, class Real>
+__global__ __launch_bounds__(kRedThreads) void k_batch_owned(const RunDev* __restrict__ runs,
+                                                             const uint32_t* __restrict__ ids, uint32_t rounds)
+{
+    const uint32_t run = ids[blockIdx.x];
+    const RunDev& R = runs[run];
+    const uint32_t prop_tiles = (R.n + kRedThreads - 1) / kRedThreads;
+    for (uint32_t k = 0; k < rounds; ++k) {
+        if (uniform_i32(R.ctl->status) != 0) break;  // uniform over the work-group
+        for (uint32_t t = 0; t < prop_tiles; ++t) {
+            propagate_body<Kind, Real, kRedThreads>(R, t);
+            __syncthreads();
+        }
+        // The group slots were updated by device-scope atomics in L2: drop
+        // this compute unit's cached copies before the reduction reads them.
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (uint32_t t = R.red_tiles; t-- > 0;) {
+            reduce_body(R, TileRef{run, t});
+            __syncthreads();
+        }
+        for (uint32_t t = R.red_tiles; t-- > 0;) {
+            scan_anc_body(R, TileRef{run, t});
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Standalone pieces: max of a given weight vector, reads, self-tests, setup.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void maxkey_body(const RunDev& R, const TileRef tr)
@@ -1527,6 +1564,39 @@ hipError_t launch_propagate(int kind, int precision, int lanes, const RunDev* ru
     default: return f32 ? launch_table_sized<5, float>(lanes, runs, tiles, n_tiles, st)
                         : launch_table_sized<5, double>(lanes, runs, tiles, n_tiles, st);
     }
+}
+
+hipError_t launch_owned(int kind, int precision, const RunDev* runs, const uint32_t* ids, uint32_t n_runs,
+                        uint32_t rounds, hipStream_t st)
+{
+    if (n_runs == 0 || rounds == 0) return hipSuccess;
+    const bool f32 = precision == 32;
+    const dim3 g(n_runs), b(kRedThreads);
+    switch (kind) {
+    case 0: hipLaunchKernelGGL((k_batch_owned<0, double>), g, b, 0, st, runs, ids, rounds); break;
+    case 1:
+        if (f32) hipLaunchKernelGGL((k_batch_owned<1, float>), g, b, 0, st, runs, ids, rounds);
+        else hipLaunchKernelGGL((k_batch_owned<1, double>), g, b, 0, st, runs, ids, rounds);
+        break;
+    case 2:
+        if (f32) hipLaunchKernelGGL((k_batch_owned<2, float>), g, b, 0, st, runs, ids, rounds);
+        else hipLaunchKernelGGL((k_batch_owned<2, double>), g, b, 0, st, runs, ids, rounds);
+        break;
+    case 3:
+        if (f32) hipLaunchKernelGGL((k_batch_owned<3, float>), g, b, 0, st, runs, ids, rounds);
+        else hipLaunchKernelGGL((k_batch_owned<3, double>), g, b, 0, st, runs, ids, rounds);
+        break;
+    case 4:
+        if (f32) hipLaunchKernelGGL((k_batch_owned<4, float>), g, b, 0, st, runs, ids, rounds);
+        else hipLaunchKernelGGL((k_batch_owned<4, double>), g, b, 0, st, runs, ids, rounds);
+        break;
+    case 5:
+        if (f32) hipLaunchKernelGGL((k_batch_owned<5, float>), g, b, 0, st, runs, ids, rounds);
+        else hipLaunchKernelGGL((k_batch_owned<5, double>), g, b, 0, st, runs, ids, rounds);
+        break;
+    default: return hipErrorInvalidValue;  // compiled programs take the segmented path
+    }
+    return hipGetLastError();
 }
 
 template <int Kind, class Real>

@@ -11,6 +11,10 @@ namespace pcfg {
 // and work-group size (128 or 256 lanes)
 hipError_t launch_propagate(int kind, int precision, int lanes, const RunDev* runs, const TileRef* tiles,
                             uint32_t n_tiles, hipStream_t st);
+// batch: runs owned by one work-group each (ids index runs), all `rounds`
+// rounds of a tick in one launch; kinds 0-5
+hipError_t launch_owned(int kind, int precision, const RunDev* runs, const uint32_t* ids, uint32_t n_runs,
+                        uint32_t rounds, hipStream_t st);
 // single run: the run record travels as a kernel argument
 hipError_t launch_propagate_one(int kind, int precision, const RunDev& run, hipStream_t st);
 hipError_t launch_resample_one(const RunDev& run, const RunDev* run_dev, hipStream_t st, int part);

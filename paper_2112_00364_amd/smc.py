@@ -151,6 +151,7 @@ def lib():
         "smc_batch_add": [vp, vp, u64, u64, C.POINTER(i32)],
         "smc_batch_tick": [vp, i32],
         "smc_batch_set_workgroup": [vp, i32, i32],
+        "smc_batch_set_owned": [vp, i32, i32],
         "smc_batch_poll": [vp, i32, vp, vp, vp, vp],
         "smc_batch_retire": [vp, i32],
         "smc_batch_destroy": [vp],
@@ -442,6 +443,11 @@ class Batch:
         """Lanes per propagation work-group of one run of the batch (128 or 256;
         results unchanged)."""
         _check(lib().smc_batch_set_workgroup(self._h, int(slot), int(lanes)))
+
+    def set_owned(self, slot: int, owned: bool = True):
+        """One work-group advances this run through every round of a tick
+        (built-in models of at most 4096 particles; results unchanged)."""
+        _check(lib().smc_batch_set_owned(self._h, int(slot), 1 if owned else 0))
 
     def poll(self):
         k = self.n_slots

@@ -1,4 +1,5 @@
-"""Batched runs under either propagation work-group size (a launch option):
+"""Batched runs under either propagation work-group size or owned by one
+work-group (launch options):
 results identical to the default size and to the runs alone; the batch
 autotuner's choice is a size and its cache round-trips."""
 import numpy as np
@@ -81,6 +82,91 @@ def test_batch_autotuner_caches_its_choice(smc, ctx, tmp_path):
         key = A.shape_key("clads", 32, 4096, 40)
         again = A.LaunchCache(str(tmp_path / "launch.json"))
         assert again.get(key)["lanes"] == lanes
-        assert set(again.get(key)["ms"]) == {"lanes128", "lanes256"}
+        # 4096 particles: owning by a work-group is a candidate too
+        assert set(again.get(key)["ms"]) == {"lanes128", "lanes256", "owned"}
+        choice = A.batch_launch(again, ctx, model, "clads", 32, 4096, 40)
+        assert choice["lanes"] == lanes and choice["owned"] == again.get(key)["owned"]
     finally:
         model.close()
+
+
+# --- runs owned by one work-group --------------------------------------------------------------
+
+def _owned_batch(smc, ctx, models, ns, owned, rounds=5, toggle_after=None):
+    b = smc.Batch(ctx)
+    slots = [b.add(m, n, 900 + i) for i, (m, n) in enumerate(zip(models, ns))]
+    for s, o in zip(slots, owned):
+        b.set_owned(s, o)
+    for tick in range(2000):
+        b.tick(rounds)
+        if toggle_after is not None and tick + 1 == toggle_after:
+            for s, o in zip(slots, owned):
+                b.set_owned(s, not o)  # switch paths between two ticks
+        done, lz, st, steps = b.poll()
+        if done.all():
+            break
+    assert done.all()
+    b.close()
+    return [(int(st[s]), float(lz[s]), int(steps[s])) for s in slots]
+
+
+def _owned_workload(smc, ctx):
+    specs = [I.geometric_spec(), I.lgssm_spec(I.lgssm_data(40, 3), 32),
+             I.crbd_spec(I.yule_tree(30, 61), precision=32), I.crbd_spec(I.yule_tree(50, 62), precision=64),
+             I.clads_spec(I.yule_tree(24, 81), precision=32), I.seir_spec(I.seir_data(12, 6001), 32),
+             dict(I.crbd_ds_spec(I.yule_tree(28, 63), precision=32), ess_threshold=0.5)]
+    ns = [1, 777, 1024, 4096, 300, 500, 2000]
+    return specs, ns, [smc.Model(ctx, s) for s in specs]
+
+
+def test_owned_runs_match_runs_alone(smc, oracle, ctx):
+    """Every built-in model, sizes from 1 to 4096 particles (ragged tiles), ESS
+    resampling: owned, segmented and mixed batches, and a batch whose runs
+    switch paths between ticks, all give each run's results alone, bit for bit."""
+    specs, ns, models = _owned_workload(smc, ctx)
+    try:
+        alone = []
+        for i, (m, n) in enumerate(zip(models, ns)):
+            r = smc.Run(m, n, 900 + i)
+            st = r.run_to_end()
+            s = r.stats()
+            alone.append((int(st), float(s["log_z"]), int(s["block_steps"])))
+            r.close()
+        k = len(ns)
+        owned = _owned_batch(smc, ctx, models, ns, [True] * k)
+        mixed = _owned_batch(smc, ctx, models, ns, [i % 2 == 0 for i in range(k)], rounds=3)
+        switched = _owned_batch(smc, ctx, models, ns, [True] * k, rounds=4, toggle_after=2)
+        assert owned == alone
+        assert mixed == alone
+        assert switched == alone
+        for i in (2, 4):  # CRBD and ClaDS owned runs against the oracle too
+            ref = oracle.Run(specs[i], ns[i], 900 + i)
+            ref.run_to_end()
+            st, lz, steps = owned[i]
+            assert st == ref.status and steps == ref.block_steps
+            assert abs(lz - ref.log_z) <= 1e-9 * abs(ref.log_z)
+    finally:
+        for m in models:
+            m.close()
+
+
+def test_owned_run_limits(smc, ctx):
+    from paper_2112_00364_amd import ppl
+    crbd = smc.Model(ctx, I.crbd_spec(I.yule_tree(20, 64), precision=32))
+    img = ppl.compile_program(I.lgssm_program(I.lgssm_data(8, 2000)), 256)
+    prog = smc.Model(ctx, {"kind": "program", "precision": 64, "program": img})
+    try:
+        b = smc.Batch(ctx)
+        big = b.add(crbd, 4097, 1)
+        small_prog = b.add(prog, 64, 2)
+        with pytest.raises(smc.SMCError):
+            b.set_owned(big)
+        with pytest.raises(smc.SMCError):
+            b.set_owned(small_prog)
+        with pytest.raises(smc.SMCError):
+            b.set_owned(small_prog + 7)
+        b.set_owned(big, False)  # leaving a run segmented is always allowed
+        b.close()
+    finally:
+        crbd.close()
+        prog.close()

@@ -78,6 +78,7 @@ def _null_calls(L):
         "smc_batch_add": lambda: L.smc_batch_add(None, None, 10, 1, ctypes.byref(i)),
         "smc_batch_tick": lambda: L.smc_batch_tick(None, 1),
         "smc_batch_set_workgroup": lambda: L.smc_batch_set_workgroup(None, 0, 128),
+        "smc_batch_set_owned": lambda: L.smc_batch_set_owned(None, 0, 1),
         "smc_batch_poll": lambda: L.smc_batch_poll(None, 0, None, None, None, None),
         "smc_batch_retire": lambda: L.smc_batch_retire(None, 0),
         "smc_resample_weights": lambda: L.smc_resample_weights(None, None, 10, 1, 0, None, None),
