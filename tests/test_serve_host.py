@@ -1,5 +1,6 @@
 """Host-side scheduling helpers of the serving loop (no GPU needed)."""
 import numpy as np
+import pytest
 
 from paper_2112_00364_amd import inputs as I
 from paper_2112_00364_amd import serve as S
@@ -54,6 +55,38 @@ def test_launch_cache_keys_and_round_trip(tmp_path):
     assert d.get("x")["lanes"] == 256
     (tmp_path / "bad.json").write_text("{not json")
     assert A.LaunchCache(str(tmp_path / "bad.json")).entries == {}
+
+
+def test_batch_launch_choice_is_applied_and_cached(tmp_path):
+    """A cached launch choice is returned without timing anything, an owned
+    choice calls set_owned and a segmented one set_workgroup, and a cache entry
+    written before owning existed (no "owned" field) is not taken as a choice."""
+    from paper_2112_00364_amd import autotune as A
+    c = A.LaunchCache(str(tmp_path / "launch.json"))
+    key = A.shape_key("crbd", 32, 256, 40)
+    c.put(key, {"lanes": 256, "owned": True, "ms": {"lanes128": 3.0, "lanes256": 2.0, "owned": 1.0}})
+    # no device is touched: the model and context are never used on a cache hit
+    assert A.batch_launch(c, None, None, "crbd", 32, 256, 40) == {"lanes": 256, "owned": True}
+
+    class FakeBatch:
+        def __init__(self):
+            self.calls = []
+
+        def set_owned(self, slot, owned=True):
+            self.calls.append(("owned", slot, owned))
+
+        def set_workgroup(self, slot, lanes):
+            self.calls.append(("lanes", slot, lanes))
+
+    b = FakeBatch()
+    A.apply_batch_launch(b, 3, {"lanes": 256, "owned": True})
+    A.apply_batch_launch(b, 4, {"lanes": 128, "owned": False})
+    assert b.calls == [("owned", 3, True), ("lanes", 4, 128)]
+    # an entry without "owned" would be re-tuned: with no device that fails
+    old = A.shape_key("clads", 32, 4096, 100)
+    c.put(old, {"lanes": 128, "ms": {"lanes128": 1.0, "lanes256": 2.0}})
+    with pytest.raises(Exception):
+        A.batch_launch(c, None, None, "clads", 32, 4096, 100)
 
 
 def test_fifo_replay_queues_measured_service_times():
